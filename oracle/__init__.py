@@ -1,0 +1,37 @@
+"""CPU oracle for tensorized NEAT population evaluation.
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import or call this
+package: only the test-suite, the smoke check and the benchmark's CPU-baseline
+leg use it. It shares no code with the HIP library (kernels, headers, helpers or
+tables) and reads only the seeded synthetic inputs.
+
+It is the plain, slow definition of what the method computes, in float64
+(the paper fixes no precision), following TensorNEAT (arXiv 2504.08339):
+
+* ``genome``   - decoding the padded node/connection tensors (Section 3.1) and
+                 the feedforward transformation: topological order plus the
+                 expanded connections as per-node in-edge lists (Section 3.3).
+* ``inference`` - the calculation stage (Section 3.3): node values in
+                 topological order, f_c = w * input, f_n = act(agg(.) + b),
+                 plus the XOR fitness and MSE loss epilogues.
+* ``compat``   - the speciation compatibility distance over connection genes
+                 aligned by historical marking (Section 2.1, Appendix A).
+* ``adjoint``  - reverse-mode derivative of the calculation stage with respect
+                 to connection weights and node biases.
+* ``hyperneat``- CPPN queries over a grid substrate and the substrate forward
+                 (HyperNEAT, named in Section 4.4).
+
+Every place where the paper is silent takes one stated reading; each function's
+docstring names it.
+"""
+from .genome import (  # noqa: F401
+    CYCLE, DANGLING, DUP_CONN, DUP_NODE, INPUT_DST, MISSING_IO, OVERSIZE,
+    ACT_NAMES, AGG_NAMES, Genome, Transformed, decode, transform,
+    transform_population, transform_arrays,
+)
+from .inference import (  # noqa: F401
+    activate, activation_slope, aggregate, forward, forward_population,
+    xor_fitness, sse_loss,
+)
+from .compat import genome_genes, distance, distance_matrix  # noqa: F401
+from .adjoint import backward, backward_population  # noqa: F401
