@@ -25,7 +25,7 @@ Every place where the paper is silent takes one stated reading; each function's
 docstring names it.
 """
 from .genome import (  # noqa: F401
-    CYCLE, DANGLING, DUP_CONN, DUP_NODE, INPUT_DST, MISSING_IO, OVERSIZE,
+    CYCLE, DANGLING, DUP_CONN, DUP_NODE, INPUT_DST, MISSING_IO, OVERSIZE, BAD_ATTR,
     ACT_NAMES, AGG_NAMES, Genome, Transformed, decode, transform,
     transform_population, transform_arrays,
 )

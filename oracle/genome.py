@@ -23,9 +23,11 @@ Readings taken where the paper is silent or garbled:
   DUP_CONN (two valid connection rows with the same (in, out) keys, enabled or
   not), DUP_NODE (two node rows with one key), INPUT_DST (an enabled edge ends
   at an input key), MISSING_IO (an input or output key has no node row),
-  OVERSIZE (a ragged genome has more rows than the capacity it was declared with).
-  CYCLE is only looked for when no other bit is set (the sort needs a
-  well-formed graph).
+  OVERSIZE (a ragged genome has more rows than the capacity it was declared
+  with; it is reported alone, since such a genome is not read further),
+  BAD_ATTR (a node row holds an activation or aggregation code outside the
+  defined sets). CYCLE is only looked for when no other bit is set (the sort
+  needs a well-formed graph).
 """
 from __future__ import annotations
 
@@ -41,6 +43,7 @@ DUP_NODE = 8
 INPUT_DST = 16
 MISSING_IO = 32
 OVERSIZE = 64
+BAD_ATTR = 128
 
 # Attribute encodings of the library's input format.
 ACT_NAMES = {0: "identity", 1: "sigmoid", 2: "tanh", 3: "relu", 4: "sin",
@@ -102,17 +105,20 @@ def decode(pop, g: int) -> Genome:
     status = 0
     if getattr(pop, "node_off", None) is not None:
         if key.shape[0] > pop.N_max or cin.shape[0] > pop.C_max:
-            status |= OVERSIZE
+            return Genome(int(pop.n_in), int(pop.n_out), {}, [], OVERSIZE)
     nodes: Dict[int, Node] = {}
     for r in range(key.shape[0]):
         k = int(key[r])
         if k < 0:
             continue
+        if int(act[r]) not in ACT_NAMES or int(agg[r]) not in AGG_NAMES:
+            status |= BAD_ATTR
         if k in nodes:
             status |= DUP_NODE
             continue
         nodes[k] = Node(r, k, float(bias[r]), float(resp[r]),
-                        ACT_NAMES[int(act[r])], AGG_NAMES[int(agg[r])])
+                        ACT_NAMES.get(int(act[r]), "identity"),
+                        AGG_NAMES.get(int(agg[r]), "sum"))
     conns: List[Conn] = []
     for r in range(cin.shape[0]):
         a, b = int(cin[r]), int(cout[r])
@@ -129,6 +135,8 @@ def transform(gen: Genome) -> Transformed:
     left empty (the genome's outputs are undefined and reported as NaN).
     """
     status = gen.status
+    if status & OVERSIZE:
+        return Transformed(status, [], {}, {})
     seen = set()
     for c in gen.conns:
         if (c.kin, c.kout) in seen:

@@ -169,6 +169,8 @@ BASE_NODES = [[0, 0, 1, 0, 0], [1, 0, 1, 0, 0], [2, 0, 1, 0, 0], [7, 0, 1, 0, 0]
     (BASE_NODES, [[0, 7, 1, 1], [7, 0, 1, 1]], oracle.INPUT_DST),  # CYCLE is only looked for when no other bit is set
     (BASE_NODES + [[8, 1, 1, 0, 0]], [[0, 2, 1, 1], [0, 2, 1, 1], [2, 55, 1, 1]],
      oracle.DUP_NODE | oracle.DUP_CONN | oracle.DANGLING),
+    (BASE_NODES + [[9, 1, 1, 7, 0]], [[0, 2, 1, 1]], oracle.BAD_ATTR),
+    (BASE_NODES + [[9, 1, 1, 0, 6]], [[0, 2, 1, 1]], oracle.BAD_ATTR),
 ])
 def test_status_bits(nodes, conns, expected):
     assert _one(nodes, conns) == expected
@@ -189,4 +191,4 @@ def test_oversize_ragged():
     pop = synth.to_ragged(synth.xor_population(P=5))
     small = synth.Population(**{**pop.__dict__, "N_max": 3})
     st = [oracle.transform(oracle.decode(small, g)).status for g in range(5)]
-    assert all(s & oracle.OVERSIZE for s in st)
+    assert all(s == oracle.OVERSIZE for s in st)
