@@ -20,8 +20,9 @@ original NEAT compatibility distance over connection genes,
 * Wbar is the mean |w1 - w2| over matching genes (0 when there are none);
 * N is the larger gene count; two empty genomes are at distance 0.
 
-A genome holding two rows with the same marking has no defined gene set: its
-distances are NaN and its counts -1.
+A genome holding two rows with the same marking, or a ragged genome above its
+declared capacity, has no defined gene set: its distances are NaN and its
+counts -1.
 """
 from __future__ import annotations
 
@@ -30,12 +31,14 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-from .genome import decode
+from .genome import OVERSIZE, decode
 
 
 def genome_genes(pop, g: int) -> Optional[Dict[Tuple[int, int], float]]:
     """Marking -> weight for genome g, or None if a marking repeats."""
     gen = decode(pop, g)
+    if gen.status & OVERSIZE:
+        return None
     genes: Dict[Tuple[int, int], float] = {}
     for c in gen.conns:
         key = (c.kin, c.kout)
