@@ -1,0 +1,272 @@
+/*
+ * tensorneat_hip.h - C ABI of the MI355X (gfx950) tensorized NEAT population
+ * evaluation library (libtnhip.so).
+ *
+ * What it computes follows TensorNEAT (arXiv 2504.08339):
+ *   - the tensorized encoding of a population (Section 3.1): every genome is a
+ *     node tensor N-hat and a connection tensor C-hat padded to fixed row
+ *     capacities and stacked into P_N, P_C;
+ *   - tensorized network inference (Section 3.3), split into the
+ *     transformation (topological order + expanded connections, done once per
+ *     network) and the calculation (node values in topological order);
+ *   - the compatibility distance used to divide the population into species
+ *     (Section 2.1, Algorithm 1; coefficients in Appendix A).
+ *
+ * Conventions for every call
+ *   - All array pointers are DEVICE pointers unless stated otherwise, row-major,
+ *     allocated and owned by the caller. The library never frees caller memory.
+ *   - Every call that takes a hipStream_t is asynchronous on that stream and
+ *     never synchronises the device unless its description says so.
+ *   - Arguments are validated on the host before anything is launched; a bad
+ *     argument returns an error status and launches nothing. A launch or
+ *     runtime error observed right after launching returns TN_EHIP.
+ *   - Problems in the DATA (a cycle, a dangling key, ...) never fail a call:
+ *     they set bits in the per-genome status word (enum tn_genome_status), and
+ *     that genome's outputs, losses and gradients are NaN.
+ */
+#ifndef TENSORNEAT_HIP_H
+#define TENSORNEAT_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+
+typedef enum tn_status {
+    TN_OK = 0,
+    TN_EINVAL = 1,        /* null pointer where one is required, negative size     */
+    TN_ESHAPE = 2,        /* inconsistent sizes (e.g. too few rows for P x N_max)   */
+    TN_EUNSUPPORTED = 3,  /* above a compiled limit (TN_MAX_NODES, TN_MAX_CONNS, ...) */
+    TN_EHIP = 4,          /* HIP launch / runtime error                              */
+    TN_ENOMEM = 5         /* a library-owned allocation failed                       */
+} tn_status;
+
+/* Human-readable name of a tn_status (static string; never NULL). */
+const char* tn_status_string(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int tn_version(void);
+
+/* Compiled limits of the per-genome row capacities handled by one call. */
+#define TN_MAX_NODES 1024
+#define TN_MAX_CONNS 4096
+#define TN_MAX_IO    1024
+
+/* ------------------------------------------------------------- encodings */
+
+/* Node activation codes (node attribute f_act, Section 3.1). Definitions:
+ * identity z; sigmoid 1/(1+e^-z); tanh; relu max(0,z); sin; gaussian e^(-z^2);
+ * abs |z|. */
+enum tn_act {
+    TN_ACT_IDENTITY = 0, TN_ACT_SIGMOID = 1, TN_ACT_TANH = 2, TN_ACT_RELU = 3,
+    TN_ACT_SIN = 4, TN_ACT_GAUSSIAN = 5, TN_ACT_ABS = 6
+};
+
+/* Node aggregation codes (node attribute f_agg, Section 3.1). Over no terms
+ * every aggregation gives 0; maxabs keeps the sign of the largest-magnitude term. */
+enum tn_agg {
+    TN_AGG_SUM = 0, TN_AGG_PRODUCT = 1, TN_AGG_MAX = 2, TN_AGG_MIN = 3,
+    TN_AGG_MEAN = 4, TN_AGG_MAXABS = 5
+};
+
+/* Per-genome status bits written by tn_transform. */
+enum tn_genome_status {
+    TN_CYCLE = 1,        /* a cycle among enabled connections (feedforward only, Section 3.3);
+                            looked for only when no other bit is set                       */
+    TN_DANGLING = 2,     /* an enabled connection names a key no node row holds            */
+    TN_DUP_CONN = 4,     /* two valid connection rows share (in-key, out-key)             */
+    TN_DUP_NODE = 8,     /* two valid node rows share a key                                */
+    TN_INPUT_DST = 16,   /* an enabled connection ends at an input key                     */
+    TN_MISSING_IO = 32,  /* an input or output key has no node row                         */
+    TN_OVERSIZE = 64,    /* ragged genome with more rows than N_max / C_max (reported alone) */
+    TN_BAD_ATTR = 128    /* a node row with an activation / aggregation code out of range  */
+};
+
+/* --------------------------------------------------------- the population */
+
+/*
+ * A population in structure-of-arrays form (Section 3.1: P_N and P_C).
+ *
+ * Node row:       key (int32), bias (f32), response (f32), act (u8), agg (u8)
+ * Connection row: in-key (int32), out-key (int32), weight (f32), enabled (u8)
+ *
+ * A node row with a negative key, or a connection row with a negative in- or
+ * out-key, is an empty row (the paper's NaN padding row); empty rows may sit
+ * anywhere. Keys are historical markers: inputs are keys 0..n_in-1 and
+ * outputs n_in..n_in+n_out-1 (Appendix B, genome interface); hidden keys are
+ * any other non-negative int32. Connection endpoints are keys, not rows.
+ *
+ * Layout
+ *   padded (node_off == NULL): genome g's node rows are [g*N_max, (g+1)*N_max),
+ *     its connection rows [g*C_max, (g+1)*C_max).
+ *   ragged (node_off != NULL): genome g's node rows are [node_off[g],
+ *     node_off[g+1]) and connection rows [conn_off[g], conn_off[g+1]); both
+ *     offset arrays are device int64 [P+1] starting at 0. N_max / C_max are
+ *     then the largest row counts the call must handle (they size on-chip
+ *     buffers); a genome above them gets TN_OVERSIZE. total_nodes /
+ *     total_conns (host values) give the array lengths: node_off[P] and
+ *     conn_off[P].
+ */
+typedef struct tn_population {
+    int32_t P;            /* number of genomes, >= 0                               */
+    int32_t n_in;         /* I, >= 0                                               */
+    int32_t n_out;        /* O, >= 1                                               */
+    int32_t N_max;        /* node row capacity, 1..TN_MAX_NODES                    */
+    int32_t C_max;        /* connection row capacity, 1..TN_MAX_CONNS              */
+    int64_t total_nodes;  /* ragged only: node_off[P]; ignored when padded         */
+    int64_t total_conns;  /* ragged only: conn_off[P]; ignored when padded         */
+    const int64_t* node_off;   /* NULL (padded) or device [P+1]                    */
+    const int64_t* conn_off;   /* NULL (padded) or device [P+1]                    */
+    const int32_t* node_key;
+    const float*   node_bias;
+    const float*   node_resp;
+    const uint8_t* node_act;
+    const uint8_t* node_agg;
+    const int32_t* conn_in;
+    const int32_t* conn_out;
+    const float*   conn_w;
+    const uint8_t* conn_en;
+} tn_population;
+
+/* Host-only check of a population descriptor (pointers and sizes; the device
+ * data is not read). Returns TN_OK, TN_EINVAL, TN_ESHAPE or TN_EUNSUPPORTED. */
+int tn_validate_population(const tn_population* pop);
+
+/* --------------------------------------------------- the transformation */
+
+/*
+ * Output of the transformation (Section 3.3), per genome, in the same node /
+ * connection row blocks as the population ("node block" = the genome's node
+ * rows, "conn block" = its connection rows), plus per-genome arrays.
+ *
+ * The topological order N_order is the level-synchronous one: round r emits,
+ * in ascending node-row order, every node whose enabled in-edges all come from
+ * nodes emitted in earlier rounds; r is the node's level. The expanded
+ * connections C_exp are kept in compressed form: the enabled in-edges of the
+ * node at topological position p, in ascending connection-row order, are
+ * entries row_ptr[p] .. row_ptr[p+1]-1 of the genome's conn block.
+ *
+ *   status  [P]          tn_genome_status bits (0 = valid)
+ *   n_valid [P]          number of node positions (0 for a flagged genome)
+ *   order   node block   node row at position p; -1 for p >= n_valid
+ *   level   node block   level of position p; -1 for p >= n_valid
+ *   row_ptr node block + 1 per genome: genome g's entries start at g*(N_max+1)
+ *                        (padded) or node_off[g]+g (ragged); n_valid+1 valid
+ *                        entries, relative to the genome's conn block; the
+ *                        rest repeat the last valid entry
+ *   edge_src conn block  topological position of the edge's source node
+ *   edge_row conn block  connection row of the edge
+ *   edge_w  conn block   weight of the edge (copied bitwise)
+ *                        (edge entries past the last valid one: -1, -1, 0)
+ *   pos_bias node block  bias of the node at position p
+ *   pos_resp node block  response of the node at position p
+ *   pos_fn  node block   act | agg << 8, with bit 31 set for an input node
+ *                        (whose value is the observation, bits 16..30 = input index)
+ *   io_pos  [P][n_in+n_out] position of input key i (i < n_in) and of output key
+ *                        n_in+j at index n_in+j
+ */
+typedef struct tn_transformed {
+    int32_t* status;
+    int32_t* n_valid;
+    int32_t* order;
+    int32_t* level;
+    int32_t* row_ptr;
+    int32_t* edge_src;
+    int32_t* edge_row;
+    float*   edge_w;
+    float*   pos_bias;
+    float*   pos_resp;
+    int32_t* pos_fn;
+    int32_t* io_pos;
+} tn_transformed;
+
+/* Element counts of the tn_transformed arrays for a population (host only):
+ * node_elems (order, level, pos_*), rowptr_elems, conn_elems (edge_*),
+ * genome_elems (status, n_valid) and io_elems (io_pos). */
+typedef struct tn_transformed_elems {
+    int64_t node_elems;
+    int64_t rowptr_elems;
+    int64_t conn_elems;
+    int64_t genome_elems;
+    int64_t io_elems;
+} tn_transformed_elems;
+
+int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out);
+
+/* Transformation of every genome (Section 3.3; BaseGenome.transform of
+ * Appendix B, batched over the population). One launch, one wavefront per
+ * genome. Fills every array of *tr. */
+int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t stream);
+
+/* ------------------------------------------------------ the calculation */
+
+/*
+ * Forward pass of every genome over B observations (Section 3.3;
+ * BaseGenome.forward of Appendix B, batched over population and batch):
+ *   v[input i] = x[i];  for each other node k in topological order
+ *   v[k] = act_k(bias_k + resp_k * agg_k(w_e * v[src_e] over its in-edges));
+ *   y[j] = v[output key n_in + j].
+ * The response multiplies the aggregate (with response 1 this is the paper's
+ * f_n = f_act(f_agg + b)). Computed in float32; the sum aggregation
+ * accumulates in ascending connection-row order with fused multiply-add.
+ *
+ *   obs   observation b of genome g, component i, at
+ *         obs[g*obs_genome_stride + b*n_in + i]; obs_genome_stride = 0 shares
+ *         one [B][n_in] batch across genomes.
+ *   out   [P][B][n_out] float32.
+ * B >= 0 (B = 0 launches nothing). tr must come from tn_transform on pop.
+ */
+int tn_forward(const tn_population* pop, const tn_transformed* tr,
+               const float* obs, int64_t obs_genome_stride, int32_t B,
+               float* out, hipStream_t stream);
+
+/*
+ * Forward pass with a fused squared-error epilogue (fitness / loss):
+ *   loss[g] = offset + scale * sum_{b,j} (y[g][b][j] - target[b][j])^2
+ * with target[b][j] at target[g*target_genome_stride + b*n_out + j]
+ * (stride 0 = shared targets). XOR fitness 4 - SSE is offset 4, scale -1; the
+ * mean squared error is offset 0, scale 1/(B*n_out). out may be NULL (outputs
+ * not stored). The per-genome sum is reduced in a fixed order (deterministic).
+ */
+int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
+                    const float* obs, int64_t obs_genome_stride, int32_t B,
+                    const float* target, int64_t target_genome_stride,
+                    float scale, float offset, float* out, float* loss,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------- distance */
+
+/*
+ * Compatibility distance between every pair of genomes (Section 2.1,
+ * Algorithm 1's species division; coefficients as in Appendix A). The
+ * original NEAT form over connection genes:
+ *   delta = c1 * E / N + c2 * D / N + c3 * Wbar
+ * Genes are all valid connection rows (enabled or not) identified by the
+ * marking (in-key, out-key), ordered lexicographically. Matching genes share a
+ * marking; excess genes E are non-matching genes beyond the smaller of the two
+ * genomes' largest markings (all genes of the other genome when one has none);
+ * disjoint D are the other non-matching genes; Wbar is the mean |w1 - w2| over
+ * matching genes (0 if none); N is the larger gene count; two empty genomes are
+ * at distance 0. A genome with a repeated marking gets NaN distances and
+ * counts of -1.
+ *
+ *   workspace  device buffer of tn_distance_workspace_size() bytes
+ *   dist       [P][P] float32
+ *   excess, disjoint  [P][P] int32, may be NULL (both or neither)
+ */
+int tn_distance_workspace_size(const tn_population* pop, size_t* bytes);
+
+int tn_distance(const tn_population* pop, float c1, float c2, float c3,
+                void* workspace, float* dist, int32_t* excess, int32_t* disjoint,
+                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TENSORNEAT_HIP_H */

@@ -1,0 +1,13 @@
+"""MI355X-native tensorized NEAT population evaluation (TensorNEAT, arXiv 2504.08339).
+
+The computation lives in libtnhip.so (HIP for gfx950, C ABI in
+include/tensorneat_hip.h); this package marshals torch tensors to it. Importing
+the package loads the library and fails loudly if it has not been built.
+"""
+from ._abi import (  # noqa: F401
+    TNError, TN_CYCLE, TN_DANGLING, TN_DUP_CONN, TN_DUP_NODE, TN_INPUT_DST, TN_MISSING_IO,
+    TN_OVERSIZE, TN_BAD_ATTR, TN_MAX_NODES, TN_MAX_CONNS,
+)
+from .api import (  # noqa: F401
+    Population, Transformed, DistanceWorkspace, transform, forward, forward_loss, distance, lib,
+)

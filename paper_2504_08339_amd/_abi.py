@@ -1,0 +1,92 @@
+"""ctypes mirror of include/tensorneat_hip.h and the loader of libtnhip.so.
+
+Argument marshalling only: every computation happens in the HIP library. A
+missing library is an ImportError (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnhip.so")
+
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_int64_p = ctypes.POINTER(ctypes.c_int64)
+c_float_p = ctypes.POINTER(ctypes.c_float)
+c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+TN_OK, TN_EINVAL, TN_ESHAPE, TN_EUNSUPPORTED, TN_EHIP, TN_ENOMEM = range(6)
+TN_MAX_NODES, TN_MAX_CONNS, TN_MAX_IO = 1024, 4096, 1024
+
+# per-genome status bits
+TN_CYCLE, TN_DANGLING, TN_DUP_CONN, TN_DUP_NODE = 1, 2, 4, 8
+TN_INPUT_DST, TN_MISSING_IO, TN_OVERSIZE, TN_BAD_ATTR = 16, 32, 64, 128
+
+
+class TnPopulation(ctypes.Structure):
+    _fields_ = [
+        ("P", ctypes.c_int32), ("n_in", ctypes.c_int32), ("n_out", ctypes.c_int32),
+        ("N_max", ctypes.c_int32), ("C_max", ctypes.c_int32),
+        ("total_nodes", ctypes.c_int64), ("total_conns", ctypes.c_int64),
+        ("node_off", c_int64_p), ("conn_off", c_int64_p),
+        ("node_key", c_int32_p), ("node_bias", c_float_p), ("node_resp", c_float_p),
+        ("node_act", c_uint8_p), ("node_agg", c_uint8_p),
+        ("conn_in", c_int32_p), ("conn_out", c_int32_p), ("conn_w", c_float_p),
+        ("conn_en", c_uint8_p),
+    ]
+
+
+class TnTransformed(ctypes.Structure):
+    _fields_ = [(n, c_int32_p) for n in ("status", "n_valid", "order", "level", "row_ptr",
+                                         "edge_src", "edge_row")] + [
+        ("edge_w", c_float_p), ("pos_bias", c_float_p), ("pos_resp", c_float_p),
+        ("pos_fn", c_int32_p), ("io_pos", c_int32_p)]
+
+
+class TnTransformedElems(ctypes.Structure):
+    _fields_ = [("node_elems", ctypes.c_int64), ("rowptr_elems", ctypes.c_int64),
+                ("conn_elems", ctypes.c_int64), ("genome_elems", ctypes.c_int64),
+                ("io_elems", ctypes.c_int64)]
+
+
+_POP = ctypes.POINTER(TnPopulation)
+_TR = ctypes.POINTER(TnTransformed)
+_STREAM = ctypes.c_void_p
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "tn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tn_version": (ctypes.c_int, []),
+    "tn_validate_population": (ctypes.c_int, [_POP]),
+    "tn_transformed_size": (ctypes.c_int, [_POP, ctypes.POINTER(TnTransformedElems)]),
+    "tn_transform": (ctypes.c_int, [_POP, _TR, _STREAM]),
+    "tn_forward": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                  c_float_p, _STREAM]),
+    "tn_forward_loss": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                       c_float_p, ctypes.c_int64, ctypes.c_float,
+                                       ctypes.c_float, c_float_p, c_float_p, _STREAM]),
+    "tn_distance_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_distance": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_void_p, c_float_p, c_int32_p, c_int32_p, _STREAM]),
+}
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(
+            f"libtnhip.so not found at {path}; build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'` "
+            "(or python paper_2504_08339_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+class TNError(RuntimeError):
+    def __init__(self, call: str, code: int, text: str):
+        super().__init__(f"{call} failed: {text} ({code})")
+        self.code = code

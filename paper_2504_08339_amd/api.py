@@ -1,0 +1,196 @@
+"""Python face of libtnhip: torch tensors in, device pointers out.
+
+Each function allocates its outputs as torch tensors on the population's device,
+passes raw pointers and torch's current HIP stream to the C ABI, and raises
+TNError on a non-zero status. No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import TNError, TnPopulation, TnTransformed, TnTransformedElems
+
+_lib = _abi.load()
+
+_NODE = {"node_key": torch.int32, "node_bias": torch.float32, "node_resp": torch.float32,
+         "node_act": torch.uint8, "node_agg": torch.uint8}
+_CONN = {"conn_in": torch.int32, "conn_out": torch.int32, "conn_w": torch.float32,
+         "conn_en": torch.uint8}
+
+
+def lib():
+    return _lib
+
+
+def _p(t, ctype):
+    return None if t is None else ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctype)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(name, rc):
+    if rc != _abi.TN_OK:
+        raise TNError(name, rc, _lib.tn_status_string(rc).decode())
+
+
+class Population:
+    """A device-resident population in the library's structure-of-arrays layout.
+
+    Padded: every node tensor is [P][N_max], every connection tensor [P][C_max].
+    Ragged: flat tensors plus int64 ``node_off`` / ``conn_off`` of length P+1.
+    """
+
+    def __init__(self, n_in: int, n_out: int, N_max: int, C_max: int, tensors: dict,
+                 node_off: Optional[torch.Tensor] = None,
+                 conn_off: Optional[torch.Tensor] = None):
+        self.n_in, self.n_out, self.N_max, self.C_max = int(n_in), int(n_out), int(N_max), int(C_max)
+        self.t = {}
+        for name, dt in {**_NODE, **_CONN}.items():
+            x = tensors[name]
+            if x.dtype != dt or not x.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous {dt} tensor")
+            self.t[name] = x
+        self.device = self.t["node_key"].device
+        self.node_off, self.conn_off = node_off, conn_off
+        if node_off is not None:
+            for o in (node_off, conn_off):
+                if o is None or o.dtype != torch.int64 or not o.is_contiguous():
+                    raise TypeError("node_off / conn_off must be contiguous int64 tensors")
+            self.P = node_off.numel() - 1
+            total_nodes, total_conns = self.t["node_key"].numel(), self.t["conn_in"].numel()
+        else:
+            self.P = self.t["node_key"].shape[0] if self.t["node_key"].dim() == 2 else 0
+            total_nodes, total_conns = self.P * self.N_max, self.P * self.C_max
+        self.c = TnPopulation(
+            self.P, self.n_in, self.n_out, self.N_max, self.C_max, total_nodes, total_conns,
+            _p(node_off, _abi.c_int64_p), _p(conn_off, _abi.c_int64_p),
+            _p(self.t["node_key"], _abi.c_int32_p), _p(self.t["node_bias"], _abi.c_float_p),
+            _p(self.t["node_resp"], _abi.c_float_p), _p(self.t["node_act"], _abi.c_uint8_p),
+            _p(self.t["node_agg"], _abi.c_uint8_p), _p(self.t["conn_in"], _abi.c_int32_p),
+            _p(self.t["conn_out"], _abi.c_int32_p), _p(self.t["conn_w"], _abi.c_float_p),
+            _p(self.t["conn_en"], _abi.c_uint8_p))
+        _check("tn_validate_population", _lib.tn_validate_population(ctypes.byref(self.c)))
+
+    @property
+    def ragged(self) -> bool:
+        return self.node_off is not None
+
+    @classmethod
+    def from_numpy(cls, n_in, n_out, N_max, C_max, arrays: dict, device="cuda",
+                   node_off=None, conn_off=None) -> "Population":
+        """Copies host arrays (names as in the C header) to ``device``."""
+        def dev(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        ts = {k: dev(arrays[k], dt) for k, dt in {**_NODE, **_CONN}.items()}
+        if node_off is not None:
+            node_off = dev(node_off, torch.int64)
+            conn_off = dev(conn_off, torch.int64)
+        return cls(n_in, n_out, N_max, C_max, ts, node_off, conn_off)
+
+
+class Transformed:
+    """Device tensors written by tn_transform (layout in the C header)."""
+
+    def __init__(self, pop: Population):
+        sz = TnTransformedElems()
+        _check("tn_transformed_size", _lib.tn_transformed_size(ctypes.byref(pop.c), ctypes.byref(sz)))
+        d = pop.device
+        i32 = dict(dtype=torch.int32, device=d)
+        f32 = dict(dtype=torch.float32, device=d)
+        self.status = torch.empty(max(sz.genome_elems, 1), **i32)
+        self.n_valid = torch.empty(max(sz.genome_elems, 1), **i32)
+        self.order = torch.empty(max(sz.node_elems, 1), **i32)
+        self.level = torch.empty(max(sz.node_elems, 1), **i32)
+        self.row_ptr = torch.empty(max(sz.rowptr_elems, 1), **i32)
+        self.edge_src = torch.empty(max(sz.conn_elems, 1), **i32)
+        self.edge_row = torch.empty(max(sz.conn_elems, 1), **i32)
+        self.edge_w = torch.empty(max(sz.conn_elems, 1), **f32)
+        self.pos_bias = torch.empty(max(sz.node_elems, 1), **f32)
+        self.pos_resp = torch.empty(max(sz.node_elems, 1), **f32)
+        self.pos_fn = torch.empty(max(sz.node_elems, 1), **i32)
+        self.io_pos = torch.empty(max(sz.io_elems, 1), **i32)
+        self.c = TnTransformed(*[_p(getattr(self, n), ty) for n, ty in (
+            ("status", _abi.c_int32_p), ("n_valid", _abi.c_int32_p), ("order", _abi.c_int32_p),
+            ("level", _abi.c_int32_p), ("row_ptr", _abi.c_int32_p), ("edge_src", _abi.c_int32_p),
+            ("edge_row", _abi.c_int32_p), ("edge_w", _abi.c_float_p), ("pos_bias", _abi.c_float_p),
+            ("pos_resp", _abi.c_float_p), ("pos_fn", _abi.c_int32_p), ("io_pos", _abi.c_int32_p))])
+
+
+def transform(pop: Population, out: Optional[Transformed] = None) -> Transformed:
+    tr = out if out is not None else Transformed(pop)
+    _check("tn_transform", _lib.tn_transform(ctypes.byref(pop.c), ctypes.byref(tr.c),
+                                             _stream(pop.device)))
+    return tr
+
+
+def _obs_stride(pop: Population, obs: torch.Tensor):
+    if obs.dtype != torch.float32 or not obs.is_contiguous():
+        raise TypeError("obs must be a contiguous float32 tensor")
+    if obs.dim() == 2:
+        return obs.shape[0], 0
+    if obs.dim() == 3 and obs.shape[0] == pop.P:
+        return obs.shape[1], obs.shape[1] * obs.shape[2]
+    raise ValueError("obs must be [B][n_in] (shared) or [P][B][n_in]")
+
+
+def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Outputs [P][B][n_out] of every genome on obs ([B][n_in] shared or [P][B][n_in])."""
+    B, stride = _obs_stride(pop, obs)
+    if out is None:
+        out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
+    _check("tn_forward", _lib.tn_forward(ctypes.byref(pop.c), ctypes.byref(tr.c),
+                                         _p(obs, _abi.c_float_p), stride, B,
+                                         _p(out, _abi.c_float_p), _stream(pop.device)))
+    return out
+
+
+def forward_loss(pop: Population, tr: Transformed, obs: torch.Tensor, target: torch.Tensor,
+                 scale: float = 1.0, offset: float = 0.0, store_outputs: bool = True):
+    """(loss [P], outputs or None): loss[g] = offset + scale * sum (y - target)^2."""
+    B, stride = _obs_stride(pop, obs)
+    if target.dim() == 2:
+        tstride = 0
+    else:
+        tstride = target.shape[1] * target.shape[2]
+    out = (torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
+           if store_outputs else None)
+    loss = torch.empty(max(pop.P, 1), dtype=torch.float32, device=pop.device)
+    _check("tn_forward_loss", _lib.tn_forward_loss(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
+        _p(target, _abi.c_float_p), tstride, scale, offset, _p(out, _abi.c_float_p),
+        _p(loss, _abi.c_float_p), _stream(pop.device)))
+    return loss[:pop.P], out
+
+
+class DistanceWorkspace:
+    def __init__(self, pop: Population):
+        n = ctypes.c_size_t()
+        _check("tn_distance_workspace_size",
+               _lib.tn_distance_workspace_size(ctypes.byref(pop.c), ctypes.byref(n)))
+        self.buf = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=pop.device)
+
+
+def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
+             counts: bool = True, workspace: Optional[DistanceWorkspace] = None, out=None):
+    """(dist [P][P], excess [P][P] or None, disjoint [P][P] or None)."""
+    ws = workspace if workspace is not None else DistanceWorkspace(pop)
+    P = pop.P
+    if out is None:
+        dist = torch.empty((P, P), dtype=torch.float32, device=pop.device)
+        E = torch.empty((P, P), dtype=torch.int32, device=pop.device) if counts else None
+        D = torch.empty((P, P), dtype=torch.int32, device=pop.device) if counts else None
+    else:
+        dist, E, D = out
+    _check("tn_distance", _lib.tn_distance(
+        ctypes.byref(pop.c), c1, c2, c3, ctypes.c_void_p(ws.buf.data_ptr()),
+        _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p), _p(D, _abi.c_int32_p),
+        _stream(pop.device)))
+    return dist, E, D

@@ -1,0 +1,168 @@
+// The extern "C" entry points of libtnhip: host-side argument validation and
+// dispatch to the launchers of each translation unit.
+#include <hip/hip_runtime.h>
+
+#include "tn_internal.hpp"
+
+namespace tn {
+
+size_t transform_lds_bytes(int N_max, int C_max);
+int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream);
+size_t forward_lds_bytes(int N_max);
+int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
+                   int64_t obs_stride, int B, float* out, hipStream_t stream);
+int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
+                        int64_t obs_stride, int B, const float* target, int64_t target_stride,
+                        float scale, float offset, float* out, float* loss, hipStream_t stream);
+size_t distance_workspace_bytes(int P, int C_max);
+int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
+                    float* dist, int32_t* E, int32_t* D, hipStream_t stream);
+
+size_t max_dynamic_lds() {
+  static size_t cached = 0;
+  if (cached) return cached;
+  int dev = 0;
+  int bytes = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+      bytes > 0)
+    cached = (size_t)bytes;
+  else
+    cached = 64 * 1024;
+  return cached;
+}
+
+namespace {
+
+int check_population(const tn_population* p) {
+  if (!p) return TN_EINVAL;
+  if (p->P < 0 || p->n_in < 0 || p->n_out < 1 || p->N_max < 1 || p->C_max < 1) return TN_EINVAL;
+  if (p->N_max > TN_MAX_NODES || p->C_max > TN_MAX_CONNS || p->n_in + p->n_out > TN_MAX_IO)
+    return TN_EUNSUPPORTED;
+  if ((p->node_off == nullptr) != (p->conn_off == nullptr)) return TN_EINVAL;
+  if (p->P == 0) return TN_OK;
+  if (!p->node_key || !p->node_bias || !p->node_resp || !p->node_act || !p->node_agg ||
+      !p->conn_in || !p->conn_out || !p->conn_w || !p->conn_en)
+    return TN_EINVAL;
+  if (p->node_off && (p->total_nodes < 0 || p->total_conns < 0)) return TN_EINVAL;
+  return TN_OK;
+}
+
+int64_t node_elems(const tn_population* p) {
+  return p->node_off ? p->total_nodes : (int64_t)p->P * p->N_max;
+}
+int64_t conn_elems(const tn_population* p) {
+  return p->node_off ? p->total_conns : (int64_t)p->P * p->C_max;
+}
+
+int check_transformed(const tn_transformed* t) {
+  if (!t) return TN_EINVAL;
+  if (!t->status || !t->n_valid || !t->order || !t->level || !t->row_ptr || !t->edge_src ||
+      !t->edge_row || !t->edge_w || !t->pos_bias || !t->pos_resp || !t->pos_fn || !t->io_pos)
+    return TN_EINVAL;
+  return TN_OK;
+}
+
+int check_obs(const tn_population* p, const float* obs, int64_t stride, int32_t B) {
+  if (B < 0 || stride < 0) return TN_EINVAL;
+  if (B > 0 && p->n_in > 0 && !obs) return TN_EINVAL;
+  if (stride > 0 && stride < (int64_t)B * p->n_in) return TN_ESHAPE;
+  return TN_OK;
+}
+
+}  // namespace
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+const char* tn_status_string(int status) {
+  switch (status) {
+    case TN_OK: return "TN_OK";
+    case TN_EINVAL: return "TN_EINVAL: invalid argument";
+    case TN_ESHAPE: return "TN_ESHAPE: inconsistent sizes";
+    case TN_EUNSUPPORTED: return "TN_EUNSUPPORTED: above a compiled or device limit";
+    case TN_EHIP: return "TN_EHIP: HIP launch or runtime error";
+    case TN_ENOMEM: return "TN_ENOMEM: allocation failed";
+    default: return "unknown tn_status";
+  }
+}
+
+int tn_version(void) { return 100; }
+
+int tn_validate_population(const tn_population* pop) { return check_population(pop); }
+
+int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (!out) return TN_EINVAL;
+  out->node_elems = node_elems(pop);
+  out->rowptr_elems = node_elems(pop) + pop->P;
+  out->conn_elems = conn_elems(pop);
+  out->genome_elems = pop->P;
+  out->io_elems = (int64_t)pop->P * (pop->n_in + pop->n_out);
+  return TN_OK;
+}
+
+int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  return launch_transform(*pop, *tr, stream);
+}
+
+int tn_forward(const tn_population* pop, const tn_transformed* tr, const float* obs,
+               int64_t obs_genome_stride, int32_t B, float* out, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (B == 0) return TN_OK;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!out) return TN_EINVAL;
+  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, stream);
+}
+
+int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const float* obs,
+                    int64_t obs_genome_stride, int32_t B, const float* target,
+                    int64_t target_genome_stride, float scale, float offset, float* out,
+                    float* loss, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (target_genome_stride < 0) return TN_EINVAL;
+  if (target_genome_stride > 0 && target_genome_stride < (int64_t)B * pop->n_out) return TN_ESHAPE;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!loss || (B > 0 && !target)) return TN_EINVAL;
+  return launch_forward_loss(*pop, *tr, obs, obs_genome_stride, B, target, target_genome_stride,
+                             scale, offset, out, loss, stream);
+}
+
+int tn_distance_workspace_size(const tn_population* pop, size_t* bytes) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (!bytes) return TN_EINVAL;
+  *bytes = distance_workspace_bytes(pop->P, pop->C_max);
+  return TN_OK;
+}
+
+int tn_distance(const tn_population* pop, float c1, float c2, float c3, void* workspace,
+                float* dist, int32_t* excess, int32_t* disjoint, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if ((excess == nullptr) != (disjoint == nullptr)) return TN_EINVAL;
+  if (pop->P > 65535) return TN_EUNSUPPORTED;
+  if (pop->P == 0) return TN_OK;
+  if (!workspace || !dist) return TN_EINVAL;
+  return launch_distance(*pop, c1, c2, c3, workspace, dist, excess, disjoint, stream);
+}
+
+}  // extern "C"

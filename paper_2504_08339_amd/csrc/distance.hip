@@ -1,0 +1,252 @@
+// Compatibility distance matrix (NEAT speciation; TensorNEAT Section 2.1,
+// Algorithm 1, coefficients of Appendix A), over connection genes identified
+// by their marking (in-key, out-key) in lexicographic order.
+//
+// Two launches:
+//   prep  one wavefront per genome: gather the valid connection rows into LDS,
+//         bitonic-sort them by marking, flag repeated markings, and store the
+//         sorted list position-major (keysT[k][g]) so that 64 genomes' k-th
+//         genes are 64 consecutive words.
+//   pairs block = one "row" genome i x 256 "column" genomes. The row genome's
+//         genes go into an LDS hash (marking -> weight) plus its sorted list.
+//         Each lane walks its column genome's sorted list (coalesced across the
+//         wavefront), probes the hash for matches (|dw| summed in ascending
+//         marking order), counts the column genes beyond the row's largest
+//         marking, and binary-searches the row's genes beyond the column's
+//         largest marking.
+#include "tn_internal.hpp"
+
+namespace tn {
+
+namespace {
+
+constexpr long long kPadKey = 0x7fffffffffffffffll;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x7feb352du;
+  k ^= k >> 15;
+  k *= 0x846ca68bu;
+  k ^= k >> 16;
+  return k;
+}
+
+__device__ __forceinline__ uint32_t hash_mark(long long k) {
+  return mix32((uint32_t)k ^ mix32((uint32_t)((unsigned long long)k >> 32)));
+}
+
+struct Ws {
+  int32_t* cnt;      // [P] gene count, -1 when a marking repeats
+  long long* maxk;   // [P] largest marking, -1 when there are none
+  long long* keysT;  // [C_max][P]
+  float* wT;         // [C_max][P]
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+Ws carve(void* base, int P, int C) {
+  unsigned char* p = (unsigned char*)base;
+  Ws w;
+  size_t o = 0;
+  w.cnt = (int32_t*)(p + o);
+  o += align_up(sizeof(int32_t) * P);
+  w.maxk = (long long*)(p + o);
+  o += align_up(sizeof(long long) * P);
+  w.keysT = (long long*)(p + o);
+  o += align_up(sizeof(long long) * (size_t)P * C);
+  w.wT = (float*)(p + o);
+  return w;
+}
+
+size_t ws_bytes(int P, int C) {
+  return align_up(sizeof(int32_t) * P) + align_up(sizeof(long long) * P) +
+         align_up(sizeof(long long) * (size_t)P * C) + align_up(sizeof(float) * (size_t)P * C);
+}
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+__global__ __launch_bounds__(kWave) void prep_kernel(PopView pop, Ws ws, int S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  long long* key = (long long*)smem;          // [S]
+  float* w = (float*)(smem + sizeof(long long) * S);  // [S]
+  __shared__ int dup;
+  const int g = blockIdx.x;
+  const int lane = lane_id();
+  const int P = pop.P;
+  const int64_t cb = pop.conn_base(g);
+  const int64_t crows = pop.conn_rows(g);
+  if (crows > pop.C_max || crows < 0) {
+    if (lane == 0) {
+      ws.cnt[g] = -1;
+      ws.maxk[g] = -1;
+    }
+    return;
+  }
+  if (lane == 0) dup = 0;
+  int n = 0;
+  for (int base = 0; base < (int)crows; base += kWave) {
+    const int r = base + lane;
+    int32_t a = -1, b = -1;
+    if (r < crows) {
+      a = pop.conn_in[cb + r];
+      b = pop.conn_out[cb + r];
+    }
+    const bool valid = a >= 0 && b >= 0;
+    const uint64_t m = __ballot(valid);
+    if (valid) {
+      const int at = n + mbcnt(m);
+      key[at] = ((long long)a << 32) | (long long)(uint32_t)b;
+      w[at] = pop.conn_w[cb + r];
+    }
+    n += __popcll(m);
+  }
+  for (int i = n + lane; i < S; i += kWave) {
+    key[i] = kPadKey;
+    w[i] = 0.0f;
+  }
+  __syncthreads();
+  // bitonic sort of S entries (S is a power of two)
+  for (int k = 2; k <= S; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < S; i += kWave) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const long long ki = key[i], kj = key[ixj];
+          const bool up = (i & k) == 0;
+          if ((ki > kj) == up) {
+            key[i] = kj;
+            key[ixj] = ki;
+            const float t = w[i];
+            w[i] = w[ixj];
+            w[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = lane + 1; i < n; i += kWave)
+    if (key[i] == key[i - 1]) dup = 1;
+  __syncthreads();
+  for (int k = lane; k < n; k += kWave) {
+    ws.keysT[(int64_t)k * P + g] = key[k];
+    ws.wT[(int64_t)k * P + g] = w[k];
+  }
+  if (lane == 0) {
+    ws.cnt[g] = dup ? -1 : n;
+    ws.maxk[g] = n > 0 ? key[n - 1] : -1;
+  }
+}
+
+constexpr int kPairBlock = 256;
+
+__global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, float c1, float c2,
+                                                           float c3, float* dist, int32_t* E_out,
+                                                           int32_t* D_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  long long* hk = (long long*)smem;                                // [HC]
+  float* hw = (float*)(smem + sizeof(long long) * HC);             // [HC]
+  long long* si = (long long*)(smem + (sizeof(long long) + sizeof(float)) * HC);  // [n_i]
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * kPairBlock + threadIdx.x;
+  const int ni = ws.cnt[i];
+  const long long maxi = ws.maxk[i];
+  for (int h = threadIdx.x; h < HC; h += kPairBlock) hk[h] = -1;
+  __syncthreads();
+  for (int k = threadIdx.x; k < ni; k += kPairBlock) {
+    const long long key = ws.keysT[(int64_t)k * P + i];
+    si[k] = key;
+    uint32_t h = hash_mark(key) & (uint32_t)(HC - 1);
+    while (atomicCAS((unsigned long long*)&hk[h], ~0ull, (unsigned long long)key) != ~0ull)
+      h = (h + 1) & (uint32_t)(HC - 1);
+    hw[h] = ws.wT[(int64_t)k * P + i];
+  }
+  __syncthreads();
+  if (j >= P) return;
+  const int nj = ws.cnt[j];
+  const int64_t o = (int64_t)i * P + j;
+  if (ni < 0 || nj < 0) {
+    dist[o] = __builtin_nanf("");
+    if (E_out) {
+      E_out[o] = -1;
+      D_out[o] = -1;
+    }
+    return;
+  }
+  const long long maxj = ws.maxk[j];
+  int M = 0, ex = 0;
+  float S = 0.0f;
+  for (int k = 0; k < nj; ++k) {
+    const long long key = ws.keysT[(int64_t)k * P + j];
+    const float w = ws.wT[(int64_t)k * P + j];
+    ex += key > maxi;
+    uint32_t h = hash_mark(key) & (uint32_t)(HC - 1);
+    while (true) {
+      const long long kk = hk[h];
+      if (kk == key) {
+        ++M;
+        S += fabsf(hw[h] - w);
+        break;
+      }
+      if (kk == -1) break;
+      h = (h + 1) & (uint32_t)(HC - 1);
+    }
+  }
+  // row genes beyond the column's largest marking: ni - upper_bound(si, maxj)
+  int lo = 0, hi = ni;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (si[mid] <= maxj) lo = mid + 1;
+    else hi = mid;
+  }
+  const int E = ex + (ni - lo);
+  const int D = ni + nj - 2 * M - E;
+  const int N = max(ni, nj);
+  float d = 0.0f;
+  if (N > 0) {
+    const float fN = (float)N;
+    d = c1 * (float)E / fN + c2 * (float)D / fN + c3 * (M > 0 ? S / (float)M : 0.0f);
+  }
+  dist[o] = d;
+  if (E_out) {
+    E_out[o] = E;
+    D_out[o] = D;
+  }
+}
+
+bool g_attr = false;
+
+}  // namespace
+
+size_t distance_workspace_bytes(int P, int C_max) { return ws_bytes(P, C_max); }
+
+int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
+                    float* dist, int32_t* E, int32_t* D, hipStream_t stream) {
+  const int S = next_pow2(p.C_max);
+  const size_t prep_lds = (sizeof(long long) + sizeof(float)) * (size_t)S;
+  const int HC = next_pow2(2 * p.C_max);
+  const size_t pair_lds = (sizeof(long long) + sizeof(float)) * (size_t)HC +
+                          sizeof(long long) * (size_t)p.C_max;
+  if (prep_lds > max_dynamic_lds() || pair_lds > max_dynamic_lds()) return TN_EUNSUPPORTED;
+  if (p.P == 0) return TN_OK;
+  if (!g_attr) {
+    hipFuncSetAttribute((const void*)prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)max_dynamic_lds());
+    hipFuncSetAttribute((const void*)pair_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)max_dynamic_lds());
+    g_attr = true;
+  }
+  Ws ws = carve(workspace, p.P, p.C_max);
+  hipLaunchKernelGGL(prep_kernel, dim3(p.P), dim3(kWave), prep_lds, stream, make_view(p), ws, S);
+  if (hipGetLastError() != hipSuccess) return TN_EHIP;
+  dim3 grid((p.P + kPairBlock - 1) / kPairBlock, p.P);
+  hipLaunchKernelGGL(pair_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HC, c1, c2,
+                     c3, dist, E, D);
+  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+}
+
+}  // namespace tn

@@ -1,0 +1,376 @@
+// Transformation stage of tensorized inference (TensorNEAT Section 3.3):
+// per genome, the topological order N_order and the expanded connections
+// C_exp, the latter kept as a compressed in-edge list per topological position.
+//
+// One wavefront (64 lanes) per genome; everything for the genome lives in LDS:
+//   1. node keys -> rows through an open-addressing hash (duplicate keys flagged)
+//   2. connection markings (in-key, out-key) through a 64-bit hash (duplicates
+//      flagged), enabled rows resolved to (source row, destination row)
+//   3. level-synchronous Kahn sort: each round takes a ballot over the node
+//      rows whose remaining in-degree is 0, places them by mbcnt in ascending
+//      row order, then decrements their successors through an out-edge list
+//   4. in-edge lists grouped by destination position: rows are dropped into
+//      buckets with LDS atomics, then each edge computes its rank among the
+//      bucket's rows, which makes the result independent of atomic order.
+#include "tn_internal.hpp"
+
+namespace tn {
+
+namespace {
+
+constexpr int32_t kEmptyKey = -1;
+constexpr unsigned long long kEmptyMark = ~0ull;
+
+__device__ __forceinline__ uint32_t hash32(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x7feb352du;
+  k ^= k >> 15;
+  k *= 0x846ca68bu;
+  k ^= k >> 16;
+  return k;
+}
+
+__device__ __forceinline__ uint32_t hash64(unsigned long long k) {
+  return hash32((uint32_t)k ^ hash32((uint32_t)(k >> 32)));
+}
+
+struct Layout {
+  int HN, HC;              // hash table sizes (powers of two)
+  int off_hkey, off_hslot, off_nkey, off_deg, off_rem, off_outdeg, off_pos,
+      off_order, off_level, off_ptr, off_cursor, off_outlist, off_esrc, off_edst,
+      off_tmp, off_chash;
+  size_t bytes;
+};
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+Layout make_layout(int N, int C) {
+  Layout L;
+  L.HN = next_pow2(2 * N);
+  L.HC = next_pow2(2 * C);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (bytes + 15) & ~size_t(15);
+    return (int)at;
+  };
+  L.off_chash = take(sizeof(unsigned long long) * L.HC);  // 8-byte aligned first
+  L.off_hkey = take(sizeof(int32_t) * L.HN);
+  L.off_hslot = take(sizeof(int16_t) * L.HN);
+  L.off_nkey = take(sizeof(int32_t) * N);
+  L.off_deg = take(sizeof(int32_t) * N);
+  L.off_rem = take(sizeof(int32_t) * N);
+  L.off_outdeg = take(sizeof(int32_t) * N);
+  L.off_pos = take(sizeof(int16_t) * N);
+  L.off_order = take(sizeof(int16_t) * N);
+  L.off_level = take(sizeof(int16_t) * N);
+  L.off_ptr = take(sizeof(int32_t) * (N + 1));
+  L.off_cursor = take(sizeof(int32_t) * N);
+  L.off_outlist = take(sizeof(int16_t) * C);
+  L.off_esrc = take(sizeof(int16_t) * C);
+  L.off_edst = take(sizeof(int16_t) * C);
+  L.off_tmp = take(sizeof(int16_t) * C);
+  L.bytes = o;
+  return L;
+}
+
+__device__ int lookup_node(const int32_t* hkey, const int16_t* hslot, int HN, int32_t k) {
+  if (k < 0) return -1;
+  uint32_t h = hash32((uint32_t)k) & (uint32_t)(HN - 1);
+  while (true) {
+    int32_t kk = hkey[h];
+    if (kk == k) return hslot[h];
+    if (kk == kEmptyKey) return -1;
+    h = (h + 1) & (uint32_t)(HN - 1);
+  }
+}
+
+// Writes the "no valid transformation" form of genome g.
+__device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int st,
+                              int64_t nb, int64_t nrows, int64_t cb, int64_t crows) {
+  const int lane = lane_id();
+  const int64_t rb = pop.rowptr_base(g);
+  for (int64_t p = lane; p < nrows; p += kWave) {
+    tr.order[nb + p] = -1;
+    tr.level[nb + p] = -1;
+    tr.pos_bias[nb + p] = 0.0f;
+    tr.pos_resp[nb + p] = 0.0f;
+    tr.pos_fn[nb + p] = 0;
+  }
+  for (int64_t p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = 0;
+  for (int64_t e = lane; e < crows; e += kWave) {
+    tr.edge_src[cb + e] = -1;
+    tr.edge_row[cb + e] = -1;
+    tr.edge_w[cb + e] = 0.0f;
+  }
+  const int nio = pop.n_in + pop.n_out;
+  for (int k = lane; k < nio; k += kWave) tr.io_pos[(int64_t)g * nio + k] = -1;
+  if (lane == 0) {
+    tr.status[g] = st;
+    tr.n_valid[g] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr, Layout L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int flags;
+
+  const int g = blockIdx.x;
+  const int lane = lane_id();
+  const int N = pop.N_max, C = pop.C_max;
+
+  const int64_t nb = pop.node_base(g);
+  const int64_t cb = pop.conn_base(g);
+  const int64_t nrows64 = pop.node_rows(g);
+  const int64_t crows64 = pop.conn_rows(g);
+  if (nrows64 > N || crows64 > C || nrows64 < 0 || crows64 < 0) {
+    write_flagged(pop, tr, g, TN_OVERSIZE, nb, nrows64 > 0 ? nrows64 : 0, cb,
+                  crows64 > 0 ? crows64 : 0);
+    return;
+  }
+  const int nrows = (int)nrows64, crows = (int)crows64;
+
+  unsigned long long* chash = (unsigned long long*)(smem + L.off_chash);
+  int32_t* hkey = (int32_t*)(smem + L.off_hkey);
+  int16_t* hslot = (int16_t*)(smem + L.off_hslot);
+  int32_t* nkey = (int32_t*)(smem + L.off_nkey);
+  int32_t* deg = (int32_t*)(smem + L.off_deg);
+  int32_t* rem = (int32_t*)(smem + L.off_rem);
+  int32_t* outdeg = (int32_t*)(smem + L.off_outdeg);
+  int16_t* pos_of = (int16_t*)(smem + L.off_pos);
+  int16_t* order_l = (int16_t*)(smem + L.off_order);
+  int16_t* level_l = (int16_t*)(smem + L.off_level);
+  int32_t* ptr = (int32_t*)(smem + L.off_ptr);
+  int32_t* cursor = (int32_t*)(smem + L.off_cursor);
+  int16_t* outlist = (int16_t*)(smem + L.off_outlist);
+  int16_t* esrc = (int16_t*)(smem + L.off_esrc);
+  int16_t* edst = (int16_t*)(smem + L.off_edst);
+  int16_t* tmp = (int16_t*)(smem + L.off_tmp);
+
+  for (int i = lane; i < L.HN; i += kWave) hkey[i] = kEmptyKey;
+  for (int i = lane; i < L.HC; i += kWave) chash[i] = kEmptyMark;
+  for (int i = lane; i < nrows; i += kWave) {
+    deg[i] = 0;
+    outdeg[i] = 0;
+    cursor[i] = 0;
+    pos_of[i] = -1;
+  }
+  if (lane == 0) flags = 0;
+  __syncthreads();
+
+  // 1. node rows -> hash
+  int my_valid = 0;
+  for (int r = lane; r < nrows; r += kWave) {
+    const int32_t k = pop.node_key[nb + r];
+    nkey[r] = k;
+    if (k < 0) continue;
+    ++my_valid;
+    if (pop.node_act[nb + r] > TN_ACT_ABS || pop.node_agg[nb + r] > TN_AGG_MAXABS)
+      atomicOr(&flags, TN_BAD_ATTR);
+    uint32_t h = hash32((uint32_t)k) & (uint32_t)(L.HN - 1);
+    while (true) {
+      const int32_t old = atomicCAS(&hkey[h], kEmptyKey, k);
+      if (old == kEmptyKey) {
+        hslot[h] = (int16_t)r;
+        break;
+      }
+      if (old == k) {
+        atomicOr(&flags, TN_DUP_NODE);
+        break;
+      }
+      h = (h + 1) & (uint32_t)(L.HN - 1);
+    }
+  }
+  const int n_valid = wave_sum_int(my_valid);
+  __syncthreads();
+
+  // 2. inputs / outputs present
+  const int nio = pop.n_in + pop.n_out;
+  for (int k = lane; k < nio; k += kWave)
+    if (lookup_node(hkey, hslot, L.HN, k) < 0) atomicOr(&flags, TN_MISSING_IO);
+
+  // 3. connection rows
+  for (int r = lane; r < crows; r += kWave) {
+    const int32_t a = pop.conn_in[cb + r];
+    const int32_t b = pop.conn_out[cb + r];
+    int16_t s = -1, d = -1;
+    if (a >= 0 && b >= 0) {
+      const unsigned long long mark = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
+      uint32_t h = hash64(mark) & (uint32_t)(L.HC - 1);
+      while (true) {
+        const unsigned long long old = atomicCAS(&chash[h], kEmptyMark, mark);
+        if (old == kEmptyMark) break;
+        if (old == mark) {
+          atomicOr(&flags, TN_DUP_CONN);
+          break;
+        }
+        h = (h + 1) & (uint32_t)(L.HC - 1);
+      }
+      if (pop.conn_en[cb + r]) {
+        const int sa = lookup_node(hkey, hslot, L.HN, a);
+        const int sb = lookup_node(hkey, hslot, L.HN, b);
+        if (sa < 0 || sb < 0) atomicOr(&flags, TN_DANGLING);
+        if (b < pop.n_in) atomicOr(&flags, TN_INPUT_DST);
+        if (sa >= 0 && sb >= 0) {
+          s = (int16_t)sa;
+          d = (int16_t)sb;
+          atomicAdd(&deg[sb], 1);
+          atomicAdd(&outdeg[sa], 1);
+        }
+      }
+    }
+    esrc[r] = s;
+    edst[r] = d;
+  }
+  __syncthreads();
+  const int st = flags;
+  if (st) {
+    write_flagged(pop, tr, g, st, nb, nrows, cb, crows);
+    return;
+  }
+
+  // 4. out-edge lists by source row
+  {
+    int carry = 0;
+    for (int base = 0; base < nrows; base += kWave) {
+      const int i = base + lane;
+      const int x = i < nrows ? outdeg[i] : 0;
+      const int inc = wave_inclusive_scan(x);
+      if (i < nrows) {
+        ptr[i] = carry + inc - x;
+        rem[i] = deg[i];
+      }
+      carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) ptr[nrows] = carry;
+  }
+  __syncthreads();
+  for (int r = lane; r < crows; r += kWave) {
+    const int s = esrc[r];
+    if (s >= 0) outlist[ptr[s] + atomicAdd(&cursor[s], 1)] = edst[r];
+  }
+  __syncthreads();
+
+  // 5. level-synchronous Kahn rounds
+  int emitted = 0;
+  for (int lvl = 0;; ++lvl) {
+    const int start = emitted;
+    for (int base = 0; base < nrows; base += kWave) {
+      const int i = base + lane;
+      const bool ready = i < nrows && nkey[i] >= 0 && pos_of[i] < 0 && rem[i] == 0;
+      const uint64_t m = __ballot(ready);
+      if (ready) {
+        const int p = emitted + mbcnt(m);
+        pos_of[i] = (int16_t)p;
+        order_l[p] = (int16_t)i;
+        level_l[p] = (int16_t)lvl;
+      }
+      emitted += __popcll(m);
+    }
+    if (emitted == start) break;
+    __syncthreads();
+    for (int p = start + lane; p < emitted; p += kWave) {
+      const int s = order_l[p];
+      for (int j = ptr[s]; j < ptr[s + 1]; ++j) atomicSub(&rem[outlist[j]], 1);
+    }
+    __syncthreads();
+  }
+  if (emitted < n_valid) {
+    write_flagged(pop, tr, g, TN_CYCLE, nb, nrows, cb, crows);
+    return;
+  }
+
+  // 6. in-edge row pointers over topological positions
+  __syncthreads();
+  {
+    int carry = 0;
+    for (int base = 0; base < n_valid; base += kWave) {
+      const int p = base + lane;
+      const int x = p < n_valid ? deg[order_l[p]] : 0;
+      const int inc = wave_inclusive_scan(x);
+      if (p < n_valid) ptr[p] = carry + inc - x;
+      carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) ptr[n_valid] = carry;
+    for (int i = lane; i < nrows; i += kWave) cursor[i] = 0;
+  }
+  __syncthreads();
+  const int n_edges = ptr[n_valid];
+  for (int r = lane; r < crows; r += kWave) {
+    const int d = edst[r];
+    if (d >= 0) tmp[ptr[pos_of[d]] + atomicAdd(&cursor[d], 1)] = (int16_t)r;
+  }
+  __syncthreads();
+
+  // 7. stable order inside each bucket, written out
+  for (int idx = lane; idx < n_edges; idx += kWave) {
+    const int r = tmp[idx];
+    const int pd = pos_of[edst[r]];
+    const int lo = ptr[pd], hi = ptr[pd + 1];
+    int rank = 0;
+    for (int j = lo; j < hi; ++j) rank += tmp[j] < r;
+    const int64_t o = cb + lo + rank;
+    tr.edge_row[o] = r;
+    tr.edge_src[o] = pos_of[esrc[r]];
+    tr.edge_w[o] = pop.conn_w[cb + r];
+  }
+  for (int e = n_edges + lane; e < crows; e += kWave) {
+    tr.edge_row[cb + e] = -1;
+    tr.edge_src[cb + e] = -1;
+    tr.edge_w[cb + e] = 0.0f;
+  }
+  const int64_t rb = pop.rowptr_base(g);
+  for (int p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = ptr[p < n_valid ? p : n_valid];
+
+  // 8. node attributes by position
+  for (int p = lane; p < nrows; p += kWave) {
+    if (p < n_valid) {
+      const int s = order_l[p];
+      tr.order[nb + p] = s;
+      tr.level[nb + p] = level_l[p];
+      tr.pos_bias[nb + p] = pop.node_bias[nb + s];
+      tr.pos_resp[nb + p] = pop.node_resp[nb + s];
+      const int k = nkey[s];
+      uint32_t fn = (uint32_t)pop.node_act[nb + s] | ((uint32_t)pop.node_agg[nb + s] << 8);
+      if (k < pop.n_in) fn = kFnInput | ((uint32_t)k << 16) | fn;
+      tr.pos_fn[nb + p] = (int32_t)fn;
+    } else {
+      tr.order[nb + p] = -1;
+      tr.level[nb + p] = -1;
+      tr.pos_bias[nb + p] = 0.0f;
+      tr.pos_resp[nb + p] = 0.0f;
+      tr.pos_fn[nb + p] = 0;
+    }
+  }
+  for (int k = lane; k < nio; k += kWave)
+    tr.io_pos[(int64_t)g * nio + k] = pos_of[lookup_node(hkey, hslot, L.HN, k)];
+  if (lane == 0) {
+    tr.status[g] = 0;
+    tr.n_valid[g] = n_valid;
+  }
+}
+
+}  // namespace
+
+size_t transform_lds_bytes(int N_max, int C_max) { return make_layout(N_max, C_max).bytes; }
+
+int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream) {
+  const Layout L = make_layout(p.N_max, p.C_max);
+  if (L.bytes > max_dynamic_lds()) return TN_EUNSUPPORTED;
+  if (p.P == 0) return TN_OK;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)transform_kernel,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds());
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(transform_kernel, dim3(p.P), dim3(kWave), L.bytes, stream,
+                     make_view(p), make_view(t), L);
+  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+}
+
+}  // namespace tn
