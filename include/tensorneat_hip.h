@@ -52,6 +52,10 @@ const char* tn_status_string(int status);
 /* Library version as 10000*major + 100*minor + patch. */
 int tn_version(void);
 
+/* Text of the last HIP error this thread's calls returned TN_EHIP for ("" if
+ * none). Static string; never NULL. */
+const char* tn_last_error(void);
+
 /* Compiled limits of the per-genome row capacities handled by one call. */
 #define TN_MAX_NODES 1024
 #define TN_MAX_CONNS 4096

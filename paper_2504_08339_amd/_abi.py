@@ -58,6 +58,7 @@ _STREAM = ctypes.c_void_p
 SIGNATURES = {
     "tn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tn_version": (ctypes.c_int, []),
+    "tn_last_error": (ctypes.c_char_p, []),
     "tn_validate_population": (ctypes.c_int, [_POP]),
     "tn_transformed_size": (ctypes.c_int, [_POP, ctypes.POINTER(TnTransformedElems)]),
     "tn_transform": (ctypes.c_int, [_POP, _TR, _STREAM]),

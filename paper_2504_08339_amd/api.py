@@ -37,7 +37,10 @@ def _stream(device) -> ctypes.c_void_p:
 
 def _check(name, rc):
     if rc != _abi.TN_OK:
-        raise TNError(name, rc, _lib.tn_status_string(rc).decode())
+        text = _lib.tn_status_string(rc).decode()
+        if rc == _abi.TN_EHIP:
+            text += f" [{_lib.tn_last_error().decode()}]"
+        raise TNError(name, rc, text)
 
 
 class Population:

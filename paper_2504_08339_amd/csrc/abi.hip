@@ -33,6 +33,23 @@ size_t max_dynamic_lds() {
 }
 
 namespace {
+thread_local hipError_t g_last_error = hipSuccess;
+}  // namespace
+
+int record_hip(hipError_t e) {
+  if (e == hipSuccess) return TN_OK;
+  g_last_error = e;
+  return TN_EHIP;
+}
+
+int allow_lds(const void* kernel, size_t bytes) {
+  if (bytes > max_dynamic_lds()) return TN_EUNSUPPORTED;
+  if (bytes <= 64 * 1024) return TN_OK;
+  return record_hip(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)bytes));
+}
+
+namespace {
 
 int check_population(const tn_population* p) {
   if (!p) return TN_EINVAL;
@@ -90,6 +107,10 @@ const char* tn_status_string(int status) {
 }
 
 int tn_version(void) { return 100; }
+
+const char* tn_last_error(void) {
+  return g_last_error == hipSuccess ? "" : hipGetErrorString(g_last_error);
+}
 
 int tn_validate_population(const tn_population* pop) { return check_population(pop); }
 

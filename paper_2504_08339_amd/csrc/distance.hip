@@ -218,8 +218,6 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
   }
 }
 
-bool g_attr = false;
-
 }  // namespace
 
 size_t distance_workspace_bytes(int P, int C_max) { return ws_bytes(P, C_max); }
@@ -231,22 +229,17 @@ int launch_distance(const tn_population& p, float c1, float c2, float c3, void* 
   const int HC = next_pow2(2 * p.C_max);
   const size_t pair_lds = (sizeof(long long) + sizeof(float)) * (size_t)HC +
                           sizeof(long long) * (size_t)p.C_max;
-  if (prep_lds > max_dynamic_lds() || pair_lds > max_dynamic_lds()) return TN_EUNSUPPORTED;
-  if (p.P == 0) return TN_OK;
-  if (!g_attr) {
-    hipFuncSetAttribute((const void*)prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)max_dynamic_lds());
-    hipFuncSetAttribute((const void*)pair_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)max_dynamic_lds());
-    g_attr = true;
-  }
+  int rc = allow_lds((const void*)prep_kernel, prep_lds);
+  if (rc == TN_OK) rc = allow_lds((const void*)pair_kernel, pair_lds);
+  if (rc != TN_OK || p.P == 0) return rc;
   Ws ws = carve(workspace, p.P, p.C_max);
   hipLaunchKernelGGL(prep_kernel, dim3(p.P), dim3(kWave), prep_lds, stream, make_view(p), ws, S);
-  if (hipGetLastError() != hipSuccess) return TN_EHIP;
+  rc = check_launch();
+  if (rc != TN_OK) return rc;
   dim3 grid((p.P + kPairBlock - 1) / kPairBlock, p.P);
   hipLaunchKernelGGL(pair_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HC, c1, c2,
                      c3, dist, E, D);
-  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+  return check_launch();
 }
 
 }  // namespace tn

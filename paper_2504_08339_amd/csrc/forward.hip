@@ -160,19 +160,9 @@ __global__ __launch_bounds__(kWave) void forward_kernel(PopView pop, TrView tr, 
   }
 }
 
-bool g_attr_set[2] = {false, false};
-
 template <bool kLoss>
 int launch(const tn_population& p, const tn_transformed& t, const FwdArgs& a, int grid) {
-  const size_t lds = (size_t)p.N_max * kWave * sizeof(float);
-  if (lds > max_dynamic_lds()) return TN_EUNSUPPORTED;
-  if (grid == 0) return TN_OK;
-  if (!g_attr_set[kLoss]) {
-    hipFuncSetAttribute((const void*)forward_kernel<kLoss>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds());
-    g_attr_set[kLoss] = true;
-  }
-  return TN_OK;
+  return allow_lds((const void*)forward_kernel<kLoss>, (size_t)p.N_max * kWave * sizeof(float));
 }
 
 }  // namespace
@@ -188,7 +178,7 @@ int launch_forward(const tn_population& p, const tn_transformed& t, const float*
   if (rc != TN_OK || grid == 0) return rc;
   hipLaunchKernelGGL(forward_kernel<false>, dim3((unsigned)grid), dim3(kWave),
                      forward_lds_bytes(p.N_max), stream, make_view(p), make_view(t), a);
-  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+  return check_launch();
 }
 
 int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
@@ -200,7 +190,7 @@ int launch_forward_loss(const tn_population& p, const tn_transformed& t, const f
   if (rc != TN_OK || p.P == 0) return rc;
   hipLaunchKernelGGL(forward_kernel<true>, dim3(p.P), dim3(kWave), forward_lds_bytes(p.N_max),
                      stream, make_view(p), make_view(t), a);
-  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+  return check_launch();
 }
 
 }  // namespace tn

@@ -137,4 +137,15 @@ __device__ __forceinline__ float activate(int act, float z) {
 // Largest dynamic LDS allocation of one workgroup on the current device.
 size_t max_dynamic_lds();
 
+// Remembers a HIP error for tn_last_error(); returns TN_OK for hipSuccess,
+// TN_EHIP otherwise.
+int record_hip(hipError_t e);
+
+// Error of the launch just issued (hipGetLastError), recorded.
+inline int check_launch() { return record_hip(hipGetLastError()); }
+
+// Lets `kernel` take `bytes` of dynamic LDS. Only requests above 64 KiB need
+// the function attribute; returns TN_EUNSUPPORTED beyond the device limit.
+int allow_lds(const void* kernel, size_t bytes);
+
 }  // namespace tn

@@ -360,17 +360,11 @@ size_t transform_lds_bytes(int N_max, int C_max) { return make_layout(N_max, C_m
 
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream) {
   const Layout L = make_layout(p.N_max, p.C_max);
-  if (L.bytes > max_dynamic_lds()) return TN_EUNSUPPORTED;
-  if (p.P == 0) return TN_OK;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)transform_kernel,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_dynamic_lds());
-    attr_set = true;
-  }
+  int rc = allow_lds((const void*)transform_kernel, L.bytes);
+  if (rc != TN_OK || p.P == 0) return rc;
   hipLaunchKernelGGL(transform_kernel, dim3(p.P), dim3(kWave), L.bytes, stream,
                      make_view(p), make_view(t), L);
-  return hipGetLastError() == hipSuccess ? TN_OK : TN_EHIP;
+  return check_launch();
 }
 
 }  // namespace tn

@@ -1,9 +1,12 @@
 """GPU parity of tn_forward / tn_forward_loss against the float64 oracle.
 
-Tolerance: |y_gpu - y_ref| <= 1e-5 * cond(y), where cond is the first-order
-error scale the oracle computes alongside the outputs (|y| plus the local
-activation slope times the propagated magnitudes |b| + |rho| * sum |w| cond);
-it is never below 1e-5 * |y_ref|. Flagged genomes must give NaN.
+Tolerance: |y_gpu - y_ref| <= 1e-5 * cond(y) + 2^-100, where cond is the
+first-order error scale the oracle computes alongside the outputs (|y| plus the
+local activation slope times the propagated magnitudes |b| + |rho| * sum |w|
+cond); it is never below 1e-5 * |y_ref|. The absolute floor 2^-100 covers values
+below float32's range: float32 underflows at 2^-126 (normal) / 2^-149
+(subnormal), and the floor allows that error to be amplified by up to 2^26
+downstream. Flagged genomes must give NaN.
 """
 import numpy as np
 import pytest
@@ -16,6 +19,7 @@ from helpers import load_golden, population_from_rows
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-5
+ABS_FLOOR = 2.0 ** -100
 
 
 def gpu_forward(pop, obs):
@@ -38,7 +42,7 @@ def check(pop, obs, Y, genomes=None):
             assert np.isnan(y).all(), g
             continue
         err = np.abs(y.astype(np.float64) - ref)
-        bad = err > RTOL * cond
+        bad = err > RTOL * cond + ABS_FLOOR
         assert not bad.any(), (g, float(err[bad].max()), float(cond[bad].min()))
         pos = cond > 0
         if pos.any():
