@@ -229,6 +229,20 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr,
                const float* obs, int64_t obs_genome_stride, int32_t B,
                float* out, hipStream_t stream);
 
+/* Tile shape of the forward pass: each wavefront evaluates one genome on
+ * tiles of 64 * obs_per_lane observations, obs_per_lane consecutive ones per
+ * lane (1, 2 or 4); a workgroup holds waves_per_genome wavefronts (1..8) of
+ * the same genome. 0 lets the library choose. Results do not depend on it. */
+typedef struct tn_tile {
+    int32_t obs_per_lane;
+    int32_t waves_per_genome;
+} tn_tile;
+
+/* tn_forward with an explicit tile shape (tile may be NULL = library choice). */
+int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr,
+                     const float* obs, int64_t obs_genome_stride, int32_t B,
+                     float* out, const tn_tile* tile, hipStream_t stream);
+
 /*
  * Forward pass with a fused squared-error epilogue (fitness / loss):
  *   loss[g] = offset + scale * sum_{b,j} (y[g][b][j] - target[b][j])^2
@@ -242,6 +256,46 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
                     const float* target, int64_t target_genome_stride,
                     float scale, float offset, float* out, float* loss,
                     hipStream_t stream);
+
+/* ---------------------------------------------------------- gradients */
+
+/*
+ * Reverse-mode gradient of the forward pass above with respect to every
+ * connection weight and node bias (gradient refinement of evolved weights;
+ * the chain rule applied to the Section 3.3 node rule). For a node k with
+ * z = bias + resp * agg(t_e), t_e = w_e * v[src_e], v = act(z):
+ *   delta_k = dL/dv_k * act'(z_k);  dL/dbias_k = sum over the batch of delta_k;
+ *   dL/dw_e = sum over the batch of delta_k * resp_k * d agg/d t_e * v_src,
+ *   and dL/dv_src accumulates delta_k * resp_k * d agg/d t_e * w_e.
+ * d agg / d t_e is 1 (sum), 1/n (mean), the product of the other terms
+ * (product), and 1 at the first extreme term in row order, 0 elsewhere (max,
+ * min, maxabs). act' at the kinks of relu and abs is 0.
+ *
+ *   dY   upstream gradient dL/dy: element (b, j) of genome g at
+ *        dY[g*dY_genome_stride + b*n_out + j]
+ *   dW   one float per connection row (the population's conn layout): the
+ *        gradient for an enabled row, exactly 0 for disabled and empty rows
+ *   db   one float per node row: the gradient for a non-input node, exactly 0
+ *        for input and empty rows
+ * The forward pass is recomputed inside the call (nothing is saved by
+ * tn_forward). Batch sums run in a fixed order, so results are deterministic.
+ * A flagged genome gets NaN in all its rows.
+ */
+int tn_backward(const tn_population* pop, const tn_transformed* tr,
+                const float* obs, int64_t obs_genome_stride, int32_t B,
+                const float* dY, int64_t dY_genome_stride,
+                float* dW, float* db, hipStream_t stream);
+
+/*
+ * Forward pass, mean-squared-error loss and its gradient in one call:
+ *   loss[g] = 1/(B*n_out) * sum_{b,j} (y[g][b][j] - target[b][j])^2
+ * (target at target[g*target_genome_stride + b*n_out + j]), and dW / db as
+ * tn_backward with dY = 2 (y - target) / (B*n_out). loss may be NULL.
+ */
+int tn_forward_backward_mse(const tn_population* pop, const tn_transformed* tr,
+                            const float* obs, int64_t obs_genome_stride, int32_t B,
+                            const float* target, int64_t target_genome_stride,
+                            float* loss, float* dW, float* db, hipStream_t stream);
 
 /* ---------------------------------------------------------- distance */
 

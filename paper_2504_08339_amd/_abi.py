@@ -50,6 +50,10 @@ class TnTransformedElems(ctypes.Structure):
                 ("io_elems", ctypes.c_int64)]
 
 
+class TnTile(ctypes.Structure):
+    _fields_ = [("obs_per_lane", ctypes.c_int32), ("waves_per_genome", ctypes.c_int32)]
+
+
 _POP = ctypes.POINTER(TnPopulation)
 _TR = ctypes.POINTER(TnTransformed)
 _STREAM = ctypes.c_void_p
@@ -64,9 +68,16 @@ SIGNATURES = {
     "tn_transform": (ctypes.c_int, [_POP, _TR, _STREAM]),
     "tn_forward": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
                                   c_float_p, _STREAM]),
+    "tn_forward_tiled": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                        c_float_p, ctypes.POINTER(TnTile), _STREAM]),
     "tn_forward_loss": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
                                        c_float_p, ctypes.c_int64, ctypes.c_float,
                                        ctypes.c_float, c_float_p, c_float_p, _STREAM]),
+    "tn_backward": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                   c_float_p, ctypes.c_int64, c_float_p, c_float_p, _STREAM]),
+    "tn_forward_backward_mse": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64,
+                                               ctypes.c_int32, c_float_p, ctypes.c_int64,
+                                               c_float_p, c_float_p, c_float_p, _STREAM]),
     "tn_distance_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(ctypes.c_size_t)]),
     "tn_distance": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_void_p, c_float_p, c_int32_p, c_int32_p, _STREAM]),

@@ -144,14 +144,18 @@ def _obs_stride(pop: Population, obs: torch.Tensor):
 
 
 def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
-            out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Outputs [P][B][n_out] of every genome on obs ([B][n_in] shared or [P][B][n_in])."""
+            out: Optional[torch.Tensor] = None, obs_per_lane: int = 0,
+            waves_per_genome: int = 0) -> torch.Tensor:
+    """Outputs [P][B][n_out] of every genome on obs ([B][n_in] shared or [P][B][n_in]).
+    ``obs_per_lane`` (1, 2, 4) and ``waves_per_genome`` (1..8) only change the
+    tile shape (0 = library choice)."""
     B, stride = _obs_stride(pop, obs)
     if out is None:
         out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
-    _check("tn_forward", _lib.tn_forward(ctypes.byref(pop.c), ctypes.byref(tr.c),
-                                         _p(obs, _abi.c_float_p), stride, B,
-                                         _p(out, _abi.c_float_p), _stream(pop.device)))
+    tile = _abi.TnTile(obs_per_lane, waves_per_genome)
+    _check("tn_forward_tiled", _lib.tn_forward_tiled(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
+        _p(out, _abi.c_float_p), ctypes.byref(tile), _stream(pop.device)))
     return out
 
 
@@ -171,6 +175,40 @@ def forward_loss(pop: Population, tr: Transformed, obs: torch.Tensor, target: to
         _p(target, _abi.c_float_p), tstride, scale, offset, _p(out, _abi.c_float_p),
         _p(loss, _abi.c_float_p), _stream(pop.device)))
     return loss[:pop.P], out
+
+
+def _grad_buffers(pop: Population):
+    dW = torch.empty_like(pop.t["conn_w"])
+    db = torch.empty_like(pop.t["node_bias"])
+    return dW, db
+
+
+def backward(pop: Population, tr: Transformed, obs: torch.Tensor, dY: torch.Tensor):
+    """(dW, db) shaped like conn_w / node_bias, for upstream gradient dY [P][B][n_out]."""
+    B, stride = _obs_stride(pop, obs)
+    if dY.dtype != torch.float32 or not dY.is_contiguous() or dY.shape != (pop.P, B, pop.n_out):
+        raise ValueError("dY must be a contiguous float32 [P][B][n_out] tensor")
+    dW, db = _grad_buffers(pop)
+    _check("tn_backward", _lib.tn_backward(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
+        _p(dY, _abi.c_float_p), B * pop.n_out, _p(dW, _abi.c_float_p), _p(db, _abi.c_float_p),
+        _stream(pop.device)))
+    return dW, db
+
+
+def forward_backward_mse(pop: Population, tr: Transformed, obs: torch.Tensor,
+                         target: torch.Tensor):
+    """(loss [P], dW, db): mean squared error against target ([B][n_out] shared or
+    [P][B][n_out]) and its gradient with respect to weights and biases."""
+    B, stride = _obs_stride(pop, obs)
+    tstride = 0 if target.dim() == 2 else target.shape[1] * target.shape[2]
+    dW, db = _grad_buffers(pop)
+    loss = torch.empty(max(pop.P, 1), dtype=torch.float32, device=pop.device)
+    _check("tn_forward_backward_mse", _lib.tn_forward_backward_mse(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
+        _p(target, _abi.c_float_p), tstride, _p(loss, _abi.c_float_p), _p(dW, _abi.c_float_p),
+        _p(db, _abi.c_float_p), _stream(pop.device)))
+    return loss[:pop.P], dW, db
 
 
 class DistanceWorkspace:

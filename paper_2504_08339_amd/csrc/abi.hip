@@ -8,12 +8,16 @@ namespace tn {
 
 size_t transform_lds_bytes(int N_max, int C_max);
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream);
-size_t forward_lds_bytes(int N_max);
+size_t forward_lds_bytes(int N_max, int C_max, int nio, int K);
 int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
-                   int64_t obs_stride, int B, float* out, hipStream_t stream);
+                   int64_t obs_stride, int B, float* out, int K, int waves, hipStream_t stream);
 int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
                         int64_t obs_stride, int B, const float* target, int64_t target_stride,
                         float scale, float offset, float* out, float* loss, hipStream_t stream);
+int launch_backward(const tn_population& p, const tn_transformed& t, const float* obs,
+                    int64_t obs_stride, int B, const float* dY, int64_t dY_stride,
+                    const float* target, int64_t target_stride, float scale, float* loss,
+                    float* dW, float* db, hipStream_t stream);
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
@@ -146,7 +150,27 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr, const float* 
   rc = check_transformed(tr);
   if (rc != TN_OK) return rc;
   if (!out) return TN_EINVAL;
-  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, stream);
+  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, 0, 0, stream);
+}
+
+int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const float* obs,
+                     int64_t obs_genome_stride, int32_t B, float* out, const tn_tile* tile,
+                     hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (tile && ((tile->obs_per_lane != 0 && tile->obs_per_lane != 1 && tile->obs_per_lane != 2 &&
+                tile->obs_per_lane != 4) ||
+               tile->waves_per_genome < 0 || tile->waves_per_genome > 8))
+    return TN_EINVAL;
+  if (pop->P == 0) return TN_OK;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (B == 0) return TN_OK;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!out) return TN_EINVAL;
+  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, tile ? tile->obs_per_lane : 0,
+                        tile ? tile->waves_per_genome : 0, stream);
 }
 
 int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const float* obs,
@@ -165,6 +189,42 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const fl
   if (!loss || (B > 0 && !target)) return TN_EINVAL;
   return launch_forward_loss(*pop, *tr, obs, obs_genome_stride, B, target, target_genome_stride,
                              scale, offset, out, loss, stream);
+}
+
+int tn_backward(const tn_population* pop, const tn_transformed* tr, const float* obs,
+                int64_t obs_genome_stride, int32_t B, const float* dY, int64_t dY_genome_stride,
+                float* dW, float* db, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (dY_genome_stride < 0) return TN_EINVAL;
+  if (dY_genome_stride > 0 && dY_genome_stride < (int64_t)B * pop->n_out) return TN_ESHAPE;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!dW || !db || (B > 0 && !dY)) return TN_EINVAL;
+  return launch_backward(*pop, *tr, obs, obs_genome_stride, B, dY, dY_genome_stride, nullptr, 0,
+                         0.0f, nullptr, dW, db, stream);
+}
+
+int tn_forward_backward_mse(const tn_population* pop, const tn_transformed* tr, const float* obs,
+                            int64_t obs_genome_stride, int32_t B, const float* target,
+                            int64_t target_genome_stride, float* loss, float* dW, float* db,
+                            hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (target_genome_stride < 0) return TN_EINVAL;
+  if (target_genome_stride > 0 && target_genome_stride < (int64_t)B * pop->n_out) return TN_ESHAPE;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!dW || !db || (B > 0 && !target)) return TN_EINVAL;
+  const float scale = B > 0 ? 1.0f / ((float)B * (float)pop->n_out) : 0.0f;
+  return launch_backward(*pop, *tr, obs, obs_genome_stride, B, nullptr, 0, target,
+                         target_genome_stride, scale, loss, dW, db, stream);
 }
 
 int tn_distance_workspace_size(const tn_population* pop, size_t* bytes) {

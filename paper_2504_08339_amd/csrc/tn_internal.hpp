@@ -93,6 +93,14 @@ __device__ __forceinline__ int mbcnt(uint64_t mask) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Orders this wavefront's LDS accesses before / after the call (the wavefront
+// only shares the LDS rows it owns; no other wavefront is waited for).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int wave_inclusive_scan(int x) {
   const int lane = lane_id();
 #pragma unroll
