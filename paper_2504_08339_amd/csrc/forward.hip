@@ -170,6 +170,17 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
   }
 
   float sse = 0.0f;
+  // Observations of the next full tile are loaded into registers while the
+  // current tile is evaluated (one tile of lookahead).
+  float pre[kMaxIn];
+  auto load_full = [&](int tt) {
+    const float* xq = obs + (int64_t)g * a.obs_stride + (int64_t)tt * kTile * I;
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j)
+      if (j < J_in) pre[j] = xq[in_off[j] >= 0 ? threadIdx.x + j * T : 0];
+  };
+  auto is_full = [&](int tt) { return tt < t_end && min(kTile, a.B - tt * kTile) == kTile; };
+  if (!st && fast_in && I > 0 && is_full(t_begin)) load_full(t_begin);
   for (int t = t_begin; t < t_end; ++t) {
     const int b0 = t * kTile;
     const int nbat = min(kTile, a.B - b0);
@@ -182,13 +193,12 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
     const bool full = nbat == kTile;
     const float* xo = obs + (int64_t)g * a.obs_stride + (int64_t)b0 * I;
     if (full && fast_in) {
-      float buf[kMaxIn];
+      if (I > 0) {
 #pragma unroll
-      for (int j = 0; j < kMaxIn; ++j)
-        if (j < J_in) buf[j] = xo[in_off[j] >= 0 ? threadIdx.x + j * T : 0];
-#pragma unroll
-      for (int j = 0; j < kMaxIn; ++j)
-        if (j < J_in && in_off[j] >= 0) vals[in_off[j]] = buf[j];
+        for (int j = 0; j < kMaxIn; ++j)
+          if (j < J_in && in_off[j] >= 0) vals[in_off[j]] = pre[j];
+        if (is_full(t + 1)) load_full(t + 1);
+      }
     } else if (I > 0) {
       const int total = nbat * I;
       DivWalk dw(threadIdx.x, I, T);
