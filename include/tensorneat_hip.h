@@ -173,6 +173,24 @@ int tn_validate_population(const tn_population* pop);
  *                        (whose value is the observation, bits 16..30 = input index)
  *   io_pos  [P][n_in+n_out] position of input key i (i < n_in) and of output key
  *                        n_in+j at index n_in+j
+ *   pos_row node block   value row of position p in the level-parallel forward
+ *                        pass's on-chip buffer: input k takes row k; level by
+ *                        level every other position takes the lowest free row,
+ *                        and rows of positions whose last consumer is in the
+ *                        level are freed after it (outputs keep theirs; a row
+ *                        freed in level L is reused from level L+1 on).
+ *                        -1 for p >= n_valid
+ *   n_rows  [P]          rows pos_row uses (<= n_valid; 0 for a flagged genome)
+ *   prog_node node block x 4 int32: packed program of the position-by-position
+ *                        forward pass: {row_ptr[p+1], node function word, bits
+ *                        of bias, bits of response}; the function word is
+ *                        act | agg << 8 | prog row << 16, or pos_fn for an input
+ *                        (whose prog row is its input index). Prog rows are
+ *                        freed right after the last consumer has read them (it
+ *                        may take one for its own value), outputs keep theirs.
+ *   prog_edge conn block x 2 int32: {prog row of the source, bits of the weight}
+ *   prog_rows [P]        rows the packed program uses (the largest number of
+ *                        values live at once; 0 for a flagged genome)
  */
 typedef struct tn_transformed {
     int32_t* status;
@@ -187,6 +205,11 @@ typedef struct tn_transformed {
     float*   pos_resp;
     int32_t* pos_fn;
     int32_t* io_pos;
+    int32_t* pos_row;
+    int32_t* n_rows;
+    int32_t* prog_node;
+    int32_t* prog_edge;
+    int32_t* prog_rows;
 } tn_transformed;
 
 /* Element counts of the tn_transformed arrays for a population (host only):
@@ -229,16 +252,33 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr,
                const float* obs, int64_t obs_genome_stride, int32_t B,
                float* out, hipStream_t stream);
 
-/* Tile shape of the forward pass: each wavefront evaluates one genome on
- * tiles of 64 * obs_per_lane observations, obs_per_lane consecutive ones per
- * lane (1, 2 or 4); a workgroup holds waves_per_genome wavefronts (1..8) of
- * the same genome. 0 lets the library choose. Results do not depend on it. */
+/* How the forward pass is laid out on the chip. Two engines:
+ *   TN_ENGINE_LDS  a workgroup of waves_per_genome wavefronts (1..8) evaluates
+ *                  one genome on tiles of 64 * obs_per_lane observations
+ *                  (obs_per_lane = 1, 2 or 4 consecutive ones per lane) with
+ *                  `rows` value rows of the tile in LDS (0: N_max), splitting
+ *                  each level of the topological order among its wavefronts;
+ *                  genomes whose n_rows exceeds `rows` get NaN outputs.
+ *   TN_ENGINE_REG  each wavefront evaluates one genome on a tile of 64
+ *                  observations with the values in registers (obs_per_lane 0
+ *                  or 1; `rows` = 32 or 64, 0: 64); waves_per_genome (1..8)
+ *                  wavefronts of one genome share a workgroup; genomes whose
+ *                  prog_rows exceeds `rows` get NaN outputs.
+ *   TN_ENGINE_AUTO the library's choice for every genome (the other fields
+ *                  are ignored): TN_ENGINE_REG for prog_rows <= 64,
+ *                  TN_ENGINE_LDS with rows = N_max for the rest.
+ * Outputs are bitwise identical across engines and tile shapes. */
+enum tn_engine { TN_ENGINE_AUTO = 0, TN_ENGINE_LDS = 1, TN_ENGINE_REG = 2 };
+
 typedef struct tn_tile {
+    int32_t engine;
     int32_t obs_per_lane;
     int32_t waves_per_genome;
+    int32_t rows;
 } tn_tile;
 
-/* tn_forward with an explicit tile shape (tile may be NULL = library choice). */
+/* tn_forward with an explicit layout (tile may be NULL: TN_ENGINE_AUTO). TN_EINVAL for
+ * field values outside the ranges above. */
 int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr,
                      const float* obs, int64_t obs_genome_stride, int32_t B,
                      float* out, const tn_tile* tile, hipStream_t stream);
@@ -256,6 +296,67 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
                     const float* target, int64_t target_genome_stride,
                     float scale, float offset, float* out, float* loss,
                     hipStream_t stream);
+
+/* ------------------------------------------------------- batched plan */
+
+/*
+ * Batched forward pass of a population whose genomes differ widely in size
+ * (the space-time trade-off of the padded encoding, Section 3.3; the
+ * population-level parallelism of Section 3.4). A plan sorts the genomes once
+ * into length buckets by the value rows their forward pass needs:
+ *   prog_rows <= 32, <= 64       TN_ENGINE_REG (one / two register banks);
+ *   n_rows <= 128, <= 256, <= the LDS capacity (about 600 rows on MI355X)
+ *                                TN_ENGINE_LDS.
+ * Flagged genomes join the first bucket (NaN outputs). Each bucket lists its
+ * genomes longest first (enabled edges + nodes).
+ *
+ * tn_plan_create reads the transformed sizes back (it synchronises `stream`)
+ * and allocates the plan's device lists, counters, streams and events; the
+ * plan keeps copies of *pop and *tr (the structs, not the arrays): the caller
+ * keeps those arrays alive and unchanged while the plan is used. tune_cache
+ * (may be NULL) is a text file written by tn_plan_tune whose tile choices are
+ * applied to matching buckets. TN_EUNSUPPORTED if a genome needs more rows
+ * than the LDS engine holds; TN_ENOMEM / TN_EHIP on allocation failures.
+ *
+ * tn_plan_forward_buckets: one plain launch per bucket, in bucket order.
+ * tn_plan_forward: one persistent kernel per bucket (its wavefronts or
+ * workgroups take the next genome or tile from a device counter, longest
+ * first) on independent branches of a hipGraph, with a zeroing kernel in
+ * front; the graph is captured on the first call and again whenever obs, its
+ * stride or out change, then replayed with one launch on `stream`. Calls on
+ * one plan must not overlap (they share its counters).
+ * Both write out [P][B][n_out] for observations laid out as in tn_forward
+ * (obs_genome_stride 0 = shared), bitwise equal to tn_forward's outputs.
+ *
+ * tn_plan_tune times every tile candidate of every bucket with plain
+ * launches (register buckets: 1, 2, 4, 8 wavefronts per workgroup; LDS
+ * buckets: 1, 2, 4 observations per lane x 1, 2, 4, 8 wavefronts), keeps the
+ * fastest, and (tune_cache != NULL) merges the choices into the cache file. It
+ * writes `out` while timing and synchronises `stream`.
+ */
+typedef struct tn_plan tn_plan;
+
+typedef struct tn_bucket_info {
+    int32_t engine;       /* TN_ENGINE_REG or TN_ENGINE_LDS */
+    int32_t rows_class;   /* REG: 32 or 64; LDS: upper bound of n_rows */
+    int32_t count;        /* genomes */
+    int64_t edges;        /* enabled edges over the bucket */
+    tn_tile tile;         /* current tile (rows: register rows / LDS rows) */
+} tn_bucket_info;
+
+int  tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B,
+                    const char* tune_cache, tn_plan** plan, hipStream_t stream);
+void tn_plan_destroy(tn_plan* plan);
+int  tn_plan_num_buckets(const tn_plan* plan);
+int  tn_plan_bucket(const tn_plan* plan, int32_t i, tn_bucket_info* info);
+/* Sets bucket i's tile: obs_per_lane (REG: 1; LDS: 1, 2, 4), waves (1..8). */
+int  tn_plan_set_tile(tn_plan* plan, int32_t i, int32_t obs_per_lane, int32_t waves);
+int  tn_plan_forward(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
+                     hipStream_t stream);
+int  tn_plan_forward_buckets(tn_plan* plan, const float* obs, int64_t obs_genome_stride,
+                             float* out, hipStream_t stream);
+int  tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
+                  const char* tune_cache, hipStream_t stream);
 
 /* ---------------------------------------------------------- gradients */
 

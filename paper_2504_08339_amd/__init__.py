@@ -6,10 +6,11 @@ the package loads the library and fails loudly if it has not been built.
 """
 from ._abi import (  # noqa: F401
     TNError, TN_CYCLE, TN_DANGLING, TN_DUP_CONN, TN_DUP_NODE, TN_INPUT_DST, TN_MISSING_IO,
-    TN_OVERSIZE, TN_BAD_ATTR, TN_MAX_NODES, TN_MAX_CONNS,
+    TN_OVERSIZE, TN_BAD_ATTR, TN_MAX_NODES, TN_MAX_CONNS, TN_ENGINE_AUTO, TN_ENGINE_LDS,
+    TN_ENGINE_REG,
 )
 from .api import (  # noqa: F401
     Population, Transformed, DistanceWorkspace, transform, forward, forward_loss, distance, lib,
-    backward, forward_backward_mse,
+    backward, forward_backward_mse, Plan,
 )
 from .autograd import TNForward  # noqa: F401

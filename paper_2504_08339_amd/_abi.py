@@ -22,6 +22,7 @@ TN_MAX_NODES, TN_MAX_CONNS, TN_MAX_IO = 1024, 4096, 1024
 # per-genome status bits
 TN_CYCLE, TN_DANGLING, TN_DUP_CONN, TN_DUP_NODE = 1, 2, 4, 8
 TN_INPUT_DST, TN_MISSING_IO, TN_OVERSIZE, TN_BAD_ATTR = 16, 32, 64, 128
+TN_ENGINE_AUTO, TN_ENGINE_LDS, TN_ENGINE_REG = 0, 1, 2
 
 
 class TnPopulation(ctypes.Structure):
@@ -41,7 +42,9 @@ class TnTransformed(ctypes.Structure):
     _fields_ = [(n, c_int32_p) for n in ("status", "n_valid", "order", "level", "row_ptr",
                                          "edge_src", "edge_row")] + [
         ("edge_w", c_float_p), ("pos_bias", c_float_p), ("pos_resp", c_float_p),
-        ("pos_fn", c_int32_p), ("io_pos", c_int32_p)]
+        ("pos_fn", c_int32_p), ("io_pos", c_int32_p), ("pos_row", c_int32_p),
+        ("n_rows", c_int32_p), ("prog_node", c_int32_p), ("prog_edge", c_int32_p),
+        ("prog_rows", c_int32_p)]
 
 
 class TnTransformedElems(ctypes.Structure):
@@ -51,7 +54,13 @@ class TnTransformedElems(ctypes.Structure):
 
 
 class TnTile(ctypes.Structure):
-    _fields_ = [("obs_per_lane", ctypes.c_int32), ("waves_per_genome", ctypes.c_int32)]
+    _fields_ = [("engine", ctypes.c_int32), ("obs_per_lane", ctypes.c_int32),
+                ("waves_per_genome", ctypes.c_int32), ("rows", ctypes.c_int32)]
+
+
+class TnBucketInfo(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("rows_class", ctypes.c_int32),
+                ("count", ctypes.c_int32), ("edges", ctypes.c_int64), ("tile", TnTile)]
 
 
 _POP = ctypes.POINTER(TnPopulation)
@@ -81,6 +90,20 @@ SIGNATURES = {
     "tn_distance_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(ctypes.c_size_t)]),
     "tn_distance": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_void_p, c_float_p, c_int32_p, c_int32_p, _STREAM]),
+    "tn_plan_create": (ctypes.c_int, [_POP, _TR, ctypes.c_int32, ctypes.c_char_p,
+                                      ctypes.POINTER(ctypes.c_void_p), _STREAM]),
+    "tn_plan_destroy": (None, [ctypes.c_void_p]),
+    "tn_plan_num_buckets": (ctypes.c_int, [ctypes.c_void_p]),
+    "tn_plan_bucket": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.POINTER(TnBucketInfo)]),
+    "tn_plan_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32]),
+    "tn_plan_forward": (ctypes.c_int, [ctypes.c_void_p, c_float_p, ctypes.c_int64, c_float_p,
+                                       _STREAM]),
+    "tn_plan_forward_buckets": (ctypes.c_int, [ctypes.c_void_p, c_float_p, ctypes.c_int64,
+                                               c_float_p, _STREAM]),
+    "tn_plan_tune": (ctypes.c_int, [ctypes.c_void_p, c_float_p, ctypes.c_int64, c_float_p,
+                                    ctypes.c_char_p, _STREAM]),
 }
 
 

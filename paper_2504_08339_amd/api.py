@@ -119,11 +119,19 @@ class Transformed:
         self.pos_resp = torch.empty(max(sz.node_elems, 1), **f32)
         self.pos_fn = torch.empty(max(sz.node_elems, 1), **i32)
         self.io_pos = torch.empty(max(sz.io_elems, 1), **i32)
+        self.pos_row = torch.empty(max(sz.node_elems, 1), **i32)
+        self.n_rows = torch.empty(max(sz.genome_elems, 1), **i32)
+        self.prog_node = torch.empty(4 * max(sz.node_elems, 1), **i32)
+        self.prog_edge = torch.empty(2 * max(sz.conn_elems, 1), **i32)
+        self.prog_rows = torch.empty(max(sz.genome_elems, 1), **i32)
         self.c = TnTransformed(*[_p(getattr(self, n), ty) for n, ty in (
             ("status", _abi.c_int32_p), ("n_valid", _abi.c_int32_p), ("order", _abi.c_int32_p),
             ("level", _abi.c_int32_p), ("row_ptr", _abi.c_int32_p), ("edge_src", _abi.c_int32_p),
             ("edge_row", _abi.c_int32_p), ("edge_w", _abi.c_float_p), ("pos_bias", _abi.c_float_p),
-            ("pos_resp", _abi.c_float_p), ("pos_fn", _abi.c_int32_p), ("io_pos", _abi.c_int32_p))])
+            ("pos_resp", _abi.c_float_p), ("pos_fn", _abi.c_int32_p), ("io_pos", _abi.c_int32_p),
+            ("pos_row", _abi.c_int32_p), ("n_rows", _abi.c_int32_p),
+            ("prog_node", _abi.c_int32_p), ("prog_edge", _abi.c_int32_p),
+            ("prog_rows", _abi.c_int32_p))])
 
 
 def transform(pop: Population, out: Optional[Transformed] = None) -> Transformed:
@@ -144,15 +152,16 @@ def _obs_stride(pop: Population, obs: torch.Tensor):
 
 
 def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
-            out: Optional[torch.Tensor] = None, obs_per_lane: int = 0,
-            waves_per_genome: int = 0) -> torch.Tensor:
+            out: Optional[torch.Tensor] = None, engine: int = 0, obs_per_lane: int = 0,
+            waves_per_genome: int = 0, rows: int = 0) -> torch.Tensor:
     """Outputs [P][B][n_out] of every genome on obs ([B][n_in] shared or [P][B][n_in]).
-    ``obs_per_lane`` (1, 2, 4) and ``waves_per_genome`` (1..8) only change the
-    tile shape (0 = library choice)."""
+    ``engine`` (TN_ENGINE_AUTO / LDS / REG), ``obs_per_lane``, ``waves_per_genome``
+    and ``rows`` only change how the work is laid out on the chip (0 = library
+    choice); a genome needing more value rows than ``rows`` gets NaN outputs."""
     B, stride = _obs_stride(pop, obs)
     if out is None:
         out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
-    tile = _abi.TnTile(obs_per_lane, waves_per_genome)
+    tile = _abi.TnTile(engine, obs_per_lane, waves_per_genome, rows)
     _check("tn_forward_tiled", _lib.tn_forward_tiled(
         ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
         _p(out, _abi.c_float_p), ctypes.byref(tile), _stream(pop.device)))
@@ -235,3 +244,66 @@ def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
         _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p), _p(D, _abi.c_int32_p),
         _stream(pop.device)))
     return dist, E, D
+
+
+class Plan:
+    """Batched forward pass over length buckets (tn_plan_*): ``forward`` replays
+    the persistent per-bucket kernels captured in a hipGraph, ``forward_buckets``
+    launches one plain kernel per bucket; both give tn_forward's bits. The
+    population and transformed tensors must stay alive and unchanged."""
+
+    def __init__(self, pop: Population, tr: Transformed, B: int,
+                 tune_cache: Optional[str] = None):
+        self.pop, self.tr, self.B = pop, tr, int(B)
+        self._h = ctypes.c_void_p()
+        _check("tn_plan_create", _lib.tn_plan_create(
+            ctypes.byref(pop.c), ctypes.byref(tr.c), self.B,
+            tune_cache.encode() if tune_cache else None, ctypes.byref(self._h),
+            _stream(pop.device)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.tn_plan_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def buckets(self):
+        out = []
+        for i in range(_lib.tn_plan_num_buckets(self._h)):
+            info = _abi.TnBucketInfo()
+            _check("tn_plan_bucket", _lib.tn_plan_bucket(self._h, i, ctypes.byref(info)))
+            out.append({"engine": info.engine, "rows_class": info.rows_class,
+                        "count": info.count, "edges": int(info.edges),
+                        "obs_per_lane": info.tile.obs_per_lane,
+                        "waves": info.tile.waves_per_genome, "rows": info.tile.rows})
+        return out
+
+    def set_tile(self, i: int, obs_per_lane: int, waves: int):
+        _check("tn_plan_set_tile", _lib.tn_plan_set_tile(self._h, i, obs_per_lane, waves))
+
+    def _call(self, name, obs, out):
+        B, stride = _obs_stride(self.pop, obs)
+        if B != self.B:
+            raise ValueError(f"the plan was made for B={self.B}, got {B}")
+        if out is None:
+            out = torch.empty((self.pop.P, B, self.pop.n_out), dtype=torch.float32,
+                              device=self.pop.device)
+        _check(name, getattr(_lib, name)(self._h, _p(obs, _abi.c_float_p), stride,
+                                         _p(out, _abi.c_float_p), _stream(self.pop.device)))
+        return out
+
+    def forward(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        return self._call("tn_plan_forward", obs, out)
+
+    def forward_buckets(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        return self._call("tn_plan_forward_buckets", obs, out)
+
+    def tune(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None,
+             tune_cache: Optional[str] = None) -> None:
+        B, stride = _obs_stride(self.pop, obs)
+        if out is None:
+            out = torch.empty((self.pop.P, B, self.pop.n_out), dtype=torch.float32,
+                              device=self.pop.device)
+        _check("tn_plan_tune", _lib.tn_plan_tune(
+            self._h, _p(obs, _abi.c_float_p), stride, _p(out, _abi.c_float_p),
+            tune_cache.encode() if tune_cache else None, _stream(self.pop.device)))

@@ -2,6 +2,9 @@
 // dispatch to the launchers of each translation unit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "fwd_launch.hpp"
 #include "tn_internal.hpp"
 
 namespace tn {
@@ -9,11 +12,6 @@ namespace tn {
 size_t transform_lds_bytes(int N_max, int C_max);
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream);
 size_t forward_lds_bytes(int N_max, int C_max, int nio, int K);
-int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
-                   int64_t obs_stride, int B, float* out, int K, int waves, hipStream_t stream);
-int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
-                        int64_t obs_stride, int B, const float* target, int64_t target_stride,
-                        float scale, float offset, float* out, float* loss, hipStream_t stream);
 int launch_backward(const tn_population& p, const tn_transformed& t, const float* obs,
                     int64_t obs_stride, int B, const float* dY, int64_t dY_stride,
                     const float* target, int64_t target_stride, float scale, float* loss,
@@ -53,8 +51,6 @@ int allow_lds(const void* kernel, size_t bytes) {
                                         (int)bytes));
 }
 
-namespace {
-
 int check_population(const tn_population* p) {
   if (!p) return TN_EINVAL;
   if (p->P < 0 || p->n_in < 0 || p->n_out < 1 || p->N_max < 1 || p->C_max < 1) return TN_EINVAL;
@@ -69,17 +65,20 @@ int check_population(const tn_population* p) {
   return TN_OK;
 }
 
+namespace {
 int64_t node_elems(const tn_population* p) {
   return p->node_off ? p->total_nodes : (int64_t)p->P * p->N_max;
 }
 int64_t conn_elems(const tn_population* p) {
   return p->node_off ? p->total_conns : (int64_t)p->P * p->C_max;
 }
+}  // namespace
 
 int check_transformed(const tn_transformed* t) {
   if (!t) return TN_EINVAL;
   if (!t->status || !t->n_valid || !t->order || !t->level || !t->row_ptr || !t->edge_src ||
-      !t->edge_row || !t->edge_w || !t->pos_bias || !t->pos_resp || !t->pos_fn || !t->io_pos)
+      !t->edge_row || !t->edge_w || !t->pos_bias || !t->pos_resp || !t->pos_fn || !t->io_pos ||
+      !t->pos_row || !t->n_rows || !t->prog_node || !t->prog_edge || !t->prog_rows)
     return TN_EINVAL;
   return TN_OK;
 }
@@ -91,7 +90,6 @@ int check_obs(const tn_population* p, const float* obs, int64_t stride, int32_t 
   return TN_OK;
 }
 
-}  // namespace
 }  // namespace tn
 
 using namespace tn;
@@ -139,18 +137,32 @@ int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t
   return launch_transform(*pop, *tr, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// TN_ENGINE_AUTO: registers for every genome whose packed program fits in 64
+// rows, the level-parallel LDS kernel for the rest (prog_rows <= N_max, so a
+// population with N_max <= 64 needs one launch).
+int forward_auto(const tn_population& p, const tn_transformed& t, const float* obs,
+                 int64_t stride, int B, float* out, hipStream_t stream) {
+  tn::RegTile rt;
+  rt.skip_above = p.N_max > 64;
+  int rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
+  if (rc != TN_OK || p.N_max <= 64) return rc;
+  tn::LdsTile lt;
+  lt.rows = std::min(p.N_max, tn::lds_rows_cap(p));
+  lt.skip_le = 64;
+  return tn::launch_forward(p, t, obs, stride, B, out, lt, tn::FwdWork(), stream);
+}
+
+}  // namespace
+
+extern "C" {
+
 int tn_forward(const tn_population* pop, const tn_transformed* tr, const float* obs,
                int64_t obs_genome_stride, int32_t B, float* out, hipStream_t stream) {
-  int rc = check_population(pop);
-  if (rc != TN_OK) return rc;
-  if (pop->P == 0) return TN_OK;
-  rc = check_obs(pop, obs, obs_genome_stride, B);
-  if (rc != TN_OK) return rc;
-  if (B == 0) return TN_OK;
-  rc = check_transformed(tr);
-  if (rc != TN_OK) return rc;
-  if (!out) return TN_EINVAL;
-  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, 0, 0, stream);
+  return tn_forward_tiled(pop, tr, obs, obs_genome_stride, B, out, nullptr, stream);
 }
 
 int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const float* obs,
@@ -158,10 +170,16 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
                      hipStream_t stream) {
   int rc = check_population(pop);
   if (rc != TN_OK) return rc;
-  if (tile && ((tile->obs_per_lane != 0 && tile->obs_per_lane != 1 && tile->obs_per_lane != 2 &&
-                tile->obs_per_lane != 4) ||
-               tile->waves_per_genome < 0 || tile->waves_per_genome > 8))
-    return TN_EINVAL;
+  const int engine = tile ? tile->engine : TN_ENGINE_AUTO;
+  if (tile) {
+    const int K = tile->obs_per_lane, W = tile->waves_per_genome, R = tile->rows;
+    if (W < 0 || W > 8 || R < 0) return TN_EINVAL;
+    if (engine == TN_ENGINE_LDS && K != 0 && K != 1 && K != 2 && K != 4) return TN_EINVAL;
+    if (engine == TN_ENGINE_REG && ((K != 0 && K != 1) || (R != 0 && R != 32 && R != 64)))
+      return TN_EINVAL;
+    if (engine != TN_ENGINE_AUTO && engine != TN_ENGINE_LDS && engine != TN_ENGINE_REG)
+      return TN_EINVAL;
+  }
   if (pop->P == 0) return TN_OK;
   rc = check_obs(pop, obs, obs_genome_stride, B);
   if (rc != TN_OK) return rc;
@@ -169,8 +187,22 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
   rc = check_transformed(tr);
   if (rc != TN_OK) return rc;
   if (!out) return TN_EINVAL;
-  return launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, tile ? tile->obs_per_lane : 0,
-                        tile ? tile->waves_per_genome : 0, stream);
+  if (engine == TN_ENGINE_LDS) {
+    tn::LdsTile lt;
+    lt.K = tile->obs_per_lane;
+    lt.waves = tile->waves_per_genome;
+    lt.rows = tile->rows;
+    return tn::launch_forward(*pop, *tr, obs, obs_genome_stride, B, out, lt, tn::FwdWork(),
+                              stream);
+  }
+  if (engine == TN_ENGINE_REG) {
+    tn::RegTile rt;
+    rt.waves = tile->waves_per_genome;
+    rt.rows = tile->rows;
+    return tn::launch_forward_reg(*pop, *tr, obs, obs_genome_stride, B, out, rt, tn::FwdWork(),
+                                  stream);
+  }
+  return forward_auto(*pop, *tr, obs, obs_genome_stride, B, out, stream);
 }
 
 int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const float* obs,
@@ -187,8 +219,13 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const fl
   rc = check_transformed(tr);
   if (rc != TN_OK) return rc;
   if (!loss || (B > 0 && !target)) return TN_EINVAL;
-  return launch_forward_loss(*pop, *tr, obs, obs_genome_stride, B, target, target_genome_stride,
-                             scale, offset, out, loss, stream);
+  const bool split = pop->N_max > 64;
+  rc = tn::launch_forward_loss_reg(*pop, *tr, obs, obs_genome_stride, B, target,
+                                   target_genome_stride, scale, offset, out, loss, 4, split,
+                                   stream);
+  if (rc != TN_OK || !split) return rc;
+  return tn::launch_forward_loss(*pop, *tr, obs, obs_genome_stride, B, target,
+                                 target_genome_stride, scale, offset, out, loss, 64, stream);
 }
 
 int tn_backward(const tn_population* pop, const tn_transformed* tr, const float* obs,

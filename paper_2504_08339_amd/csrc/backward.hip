@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
     NodeRec r;
     const int e0 = row_ptr[rb + p], e1 = row_ptr[rb + p + 1];
     r.erange = e0 | (e1 << 16);
-    r.fn = fn[nb + p];
+    r.fn = fn_with_row(fn[nb + p], p);  // one value row per position here
     r.bias = __int_as_float(bias_bits[nb + p]);
     r.resp = __int_as_float(resp_bits[nb + p]);
     recs[p] = r;

@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "fwd_core.hpp"
+#include "fwd_launch.hpp"
 
 namespace tn {
 
@@ -30,6 +31,11 @@ struct FwdArgs {
   int n_tiles;   // tiles of 64*K observations per genome
   int n_groups;  // workgroups per genome
   int per_wg;    // consecutive tiles per workgroup
+  int rows;      // value rows per tile in LDS (>= every genome's n_rows)
+  int skip_le;   // genomes with prog_rows <= skip_le are left to another launch (-1: none)
+  const int32_t* genomes;  // genome list (nullptr: every genome, in order)
+  int32_t* queue;          // persistent launch: next list entry to take
+  int n_items;             // persistent launch: list length
 };
 
 // LDS of one workgroup: level starts, io positions, [staged program], rows.
@@ -42,14 +48,15 @@ struct FwdLds {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline FwdLds fwd_lds(int N_max, int C_max, int nio, int K, bool prog_lds) {
+__host__ __device__ inline FwdLds fwd_lds(int N_max, int C_max, int nio, int K, bool prog_lds,
+                                          int rows) {
   FwdLds L;
   L.lvl_off = 0;
   L.io_off = align16(L.lvl_off + sizeof(int32_t) * (size_t)(N_max + 2));
   L.rec_off = align16(L.io_off + sizeof(int32_t) * (size_t)nio);
   L.edge_off = L.rec_off + (prog_lds ? sizeof(NodeRec) * (size_t)N_max : 0);
   L.rows_off = align16(L.edge_off + (prog_lds ? sizeof(EdgeRec) * (size_t)C_max : 0));
-  L.bytes = L.rows_off + sizeof(float) * (size_t)N_max * (kWave + 1) * K;
+  L.bytes = L.rows_off + sizeof(float) * (size_t)rows * (kWave + 1) * K;
   return L;
 }
 
@@ -63,15 +70,20 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return (bid % kXcd) * per + bid / kXcd;
 }
 
+// Whole evaluation of genome g on tiles t_begin .. t_end-1 by one workgroup.
+// Starts and ends with the workgroup's LDS free (every path ends at a
+// barrier), so a persistent workgroup can run it for genome after genome.
 template <int K, bool kLoss, bool kProgLds>
-__global__ __launch_bounds__(kWave * 8) void forward_kernel(
-    PopView pop, const int32_t* __restrict__ status, const int32_t* __restrict__ n_valid,
+__device__ __forceinline__ void lds_genome(
+    const PopView& pop, const int32_t* __restrict__ status, const int32_t* __restrict__ n_valid,
     const int32_t* __restrict__ level, const int32_t* __restrict__ row_ptr,
     const int32_t* __restrict__ src, const int32_t* __restrict__ w_bits,
     const int32_t* __restrict__ fn, const int32_t* __restrict__ bias_bits,
     const int32_t* __restrict__ resp_bits, const int32_t* __restrict__ io_pos,
-    const float* __restrict__ obs, float* __restrict__ out, const float* __restrict__ target,
-    float* __restrict__ loss, FwdArgs a) {
+    const int32_t* __restrict__ pos_row, const int32_t* __restrict__ n_rows,
+    const int32_t* __restrict__ prog_rows, const float* __restrict__ obs,
+    float* __restrict__ out, const float* __restrict__ target, float* __restrict__ loss,
+    const FwdArgs& a, int g, int t_begin, int t_end) {
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ int n_lvl_sh;
   __shared__ float part[16];
@@ -81,25 +93,16 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
   const int W = blockDim.x / kWave;
   const int T = blockDim.x;
   const int I = pop.n_in, O = pop.n_out, nio = I + O;
-  const FwdLds L = fwd_lds(pop.N_max, pop.C_max, nio, K, kProgLds);
+  const FwdLds L = fwd_lds(pop.N_max, pop.C_max, nio, K, kProgLds, a.rows);
   int32_t* lvl = reinterpret_cast<int32_t*>(lds + L.lvl_off);
   int32_t* io_l = reinterpret_cast<int32_t*>(lds + L.io_off);
   NodeRec* recs = reinterpret_cast<NodeRec*>(lds + L.rec_off);
   EdgeRec* edges = reinterpret_cast<EdgeRec*>(lds + L.edge_off);
   float* vals = reinterpret_cast<float*>(lds + L.rows_off);
 
-  int g, t_begin, t_end;
-  if (kLoss) {
-    g = blockIdx.x;
-    t_begin = 0;
-    t_end = a.n_tiles;
-  } else {
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
-    g = item / a.n_groups;
-    t_begin = (item - g * a.n_groups) * a.per_wg;
-    t_end = min(t_begin + a.per_wg, a.n_tiles);
-  }
-  const int st = status[g];
+  if (prog_rows[g] <= a.skip_le) return;  // uniform per workgroup
+  // a genome needing more rows than the launch provides is reported as NaN
+  const int st = status[g] ? status[g] : (n_rows[g] > a.rows ? -1 : 0);
   const int n = n_valid[g];
   const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
 
@@ -119,12 +122,13 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
         n_lvl_sh = cnt;
       }
     }
-    for (int k = threadIdx.x; k < nio; k += T) io_l[k] = io_pos[(int64_t)g * nio + k];
+    for (int k = threadIdx.x; k < nio; k += T)
+      io_l[k] = pos_row[nb + io_pos[(int64_t)g * nio + k]];
     if (kProgLds) {
       for (int p = threadIdx.x; p < n; p += T) {
         NodeRec r;
         r.erange = row_ptr[rb + p] | (row_ptr[rb + p + 1] << 16);
-        r.fn = fn[nb + p];
+        r.fn = fn_with_row(fn[nb + p], pos_row[nb + p]);
         r.bias = __int_as_float(bias_bits[nb + p]);
         r.resp = __int_as_float(resp_bits[nb + p]);
         recs[p] = r;
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
       const int n_edges = row_ptr[rb + n];
       for (int e = threadIdx.x; e < n_edges; e += T) {
         EdgeRec q;
-        q.src = src[cb + e];
+        q.src = pos_row[nb + src[cb + e]];
         q.w = __int_as_float(w_bits[cb + e]);
         edges[e] = q;
       }
@@ -141,7 +145,8 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
   __syncthreads();
   const int n_lvl = st ? 0 : n_lvl_sh;
   LdsProg lp{recs, edges};
-  GlobalProg gp{row_ptr + rb, fn + nb, bias_bits + nb, resp_bits + nb, src + cb, w_bits + cb};
+  GlobalProg gp{row_ptr + rb, fn + nb,     bias_bits + nb, resp_bits + nb,
+                src + cb,    w_bits + cb, pos_row + nb};
 
   constexpr int kRow = (kWave + 1) * K;  // floats per LDS row
   float* mine = vals + lane * K;
@@ -260,6 +265,55 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(
       for (int v = 0; v < W; ++v) acc += part[v];
       loss[g] = st ? __builtin_nanf("") : fmaf(a.scale, acc, a.offset);
     }
+    __syncthreads();
+  }
+}
+
+#define TN_FWD_PARAMS                                                                           \
+  PopView pop, const int32_t *__restrict__ status, const int32_t *__restrict__ n_valid,         \
+      const int32_t *__restrict__ level, const int32_t *__restrict__ row_ptr,                   \
+      const int32_t *__restrict__ src, const int32_t *__restrict__ w_bits,                      \
+      const int32_t *__restrict__ fn, const int32_t *__restrict__ bias_bits,                    \
+      const int32_t *__restrict__ resp_bits, const int32_t *__restrict__ io_pos,                \
+      const int32_t *__restrict__ pos_row, const int32_t *__restrict__ n_rows,                  \
+      const int32_t *__restrict__ prog_rows, const float *__restrict__ obs,                     \
+      float *__restrict__ out, const float *__restrict__ target, float *__restrict__ loss,      \
+      FwdArgs a
+#define TN_FWD_ARGS                                                                             \
+  pop, status, n_valid, level, row_ptr, src, w_bits, fn, bias_bits, resp_bits, io_pos, pos_row, \
+      n_rows, prog_rows, obs, out, target, loss, a
+
+// One workgroup per (genome, group of consecutive tiles).
+template <int K, bool kLoss, bool kProgLds>
+__global__ __launch_bounds__(kWave * 8) void forward_kernel(TN_FWD_PARAMS) {
+  int item, t_begin, t_end;
+  if (kLoss) {
+    item = blockIdx.x;
+    t_begin = 0;
+    t_end = a.n_tiles;
+  } else {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    item = b / a.n_groups;
+    t_begin = (b - item * a.n_groups) * a.per_wg;
+    t_end = min(t_begin + a.per_wg, a.n_tiles);
+  }
+  const int g = a.genomes ? a.genomes[item] : item;
+  lds_genome<K, kLoss, kProgLds>(TN_FWD_ARGS, g, t_begin, t_end);
+}
+
+// Persistent form: each workgroup takes the next genome of the list (longest
+// first) from a counter until the list is exhausted; the counter must be 0 at
+// launch.
+template <int K, bool kProgLds>
+__global__ __launch_bounds__(kWave * 8) void forward_queue_kernel(TN_FWD_PARAMS) {
+  __shared__ int item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_sh);
+    __syncthreads();
+    if (item >= a.n_items) break;
+    lds_genome<K, false, kProgLds>(TN_FWD_ARGS, a.genomes[item], 0, a.n_tiles);
   }
 }
 
@@ -267,29 +321,39 @@ template <int K, bool kLoss, bool kProgLds>
 int launch_k(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
              const float* target, float* loss, const FwdArgs& a, int grid, int waves,
              hipStream_t stream) {
-  const size_t lds = fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, kProgLds).bytes;
-  int rc = allow_lds((const void*)forward_kernel<K, kLoss, kProgLds>, lds);
+  const size_t lds = fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, kProgLds, a.rows).bytes;
+  const bool queue = !kLoss && a.queue;
+  const void* kern = queue ? (const void*)forward_queue_kernel<K, kProgLds>
+                           : (const void*)forward_kernel<K, kLoss, kProgLds>;
+  int rc = allow_lds(kern, lds);
   if (rc != TN_OK || grid == 0) return rc;
-  hipLaunchKernelGGL((forward_kernel<K, kLoss, kProgLds>), dim3((unsigned)grid),
-                     dim3(kWave * waves), lds, stream, make_view(p), t.status, t.n_valid,
-                     t.level, t.row_ptr, t.edge_src, reinterpret_cast<const int32_t*>(t.edge_w),
-                     t.pos_fn, reinterpret_cast<const int32_t*>(t.pos_bias),
-                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, obs, out, target,
-                     loss, a);
+#define TN_FWD_LAUNCH_ARGS                                                                   \
+  make_view(p), t.status, t.n_valid, t.level, t.row_ptr, t.edge_src,                         \
+      reinterpret_cast<const int32_t*>(t.edge_w), t.pos_fn,                                  \
+      reinterpret_cast<const int32_t*>(t.pos_bias), reinterpret_cast<const int32_t*>(t.pos_resp), \
+      t.io_pos, t.pos_row, t.n_rows, t.prog_rows, obs, out, target, loss, a
+  if (queue)
+    hipLaunchKernelGGL((forward_queue_kernel<K, kProgLds>), dim3((unsigned)grid),
+                       dim3(kWave * waves), lds, stream, TN_FWD_LAUNCH_ARGS);
+  else
+    hipLaunchKernelGGL((forward_kernel<K, kLoss, kProgLds>), dim3((unsigned)grid),
+                       dim3(kWave * waves), lds, stream, TN_FWD_LAUNCH_ARGS);
+#undef TN_FWD_LAUNCH_ARGS
   return check_launch();
 }
 
 // Program in LDS if it fits beside the rows, else read from global memory.
-bool prog_fits(const tn_population& p, int K) {
-  return fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, true).bytes <= max_dynamic_lds();
+bool prog_fits(const tn_population& p, int K, int rows) {
+  return fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, true, rows).bytes <= max_dynamic_lds();
 }
 
 template <bool kLoss>
 int dispatch(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
              const float* target, float* loss, const FwdArgs& a, int grid, int K, int waves,
              hipStream_t stream) {
-  const bool in_lds = prog_fits(p, K);
-  if (!in_lds && fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, false).bytes > max_dynamic_lds())
+  const bool in_lds = prog_fits(p, K, a.rows);
+  if (!in_lds &&
+      fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, K, false, a.rows).bytes > max_dynamic_lds())
     return TN_EUNSUPPORTED;
 #define TN_FWD_CASE(KK)                                                                     \
   case KK:                                                                                  \
@@ -308,31 +372,89 @@ int dispatch(const tn_population& p, const tn_transformed& t, const float* obs, 
 
 }  // namespace
 
+int lds_rows_cap(const tn_population& p) {
+  // largest row count the level-parallel kernel holds at one observation per lane
+  int lo = 1, hi = p.N_max;
+  if (fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, 1, false, hi).bytes <= max_dynamic_lds())
+    return hi;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (fwd_lds(p.N_max, p.C_max, p.n_in + p.n_out, 1, false, mid).bytes <= max_dynamic_lds())
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 size_t forward_lds_bytes(int N_max, int C_max, int nio, int K) {
-  return fwd_lds(N_max, C_max, nio, K, true).bytes;
+  return fwd_lds(N_max, C_max, nio, K, true, N_max).bytes;
+}
+
+size_t lds_tile_bytes(const tn_population& p, int K, int rows) {
+  const int nio = p.n_in + p.n_out;
+  const size_t with = fwd_lds(p.N_max, p.C_max, nio, K, true, rows).bytes;
+  if (with <= max_dynamic_lds()) return with;
+  const size_t without = fwd_lds(p.N_max, p.C_max, nio, K, false, rows).bytes;
+  return without <= max_dynamic_lds() ? without : 0;
+}
+
+int lds_queue_grid(const tn_population& p, int K, int waves, int rows) {
+  const size_t lds = lds_tile_bytes(p, K, rows);
+  if (lds == 0) return 0;
+  const bool in_lds = prog_fits(p, K, rows);
+  const void* k = nullptr;
+  switch (K * 2 + (in_lds ? 1 : 0)) {
+    case 2: k = (const void*)forward_queue_kernel<1, false>; break;
+    case 3: k = (const void*)forward_queue_kernel<1, true>; break;
+    case 4: k = (const void*)forward_queue_kernel<2, false>; break;
+    case 5: k = (const void*)forward_queue_kernel<2, true>; break;
+    case 8: k = (const void*)forward_queue_kernel<4, false>; break;
+    case 9: k = (const void*)forward_queue_kernel<4, true>; break;
+    default: return 0;
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  if (allow_lds(k, lds) != TN_OK) return 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWave * waves, lds);
+  if (record_hip(e) != TN_OK) return 0;
+  return std::max(1, per_cu) * cus;
 }
 
 int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
-                   int64_t obs_stride, int B, float* out, int K, int waves, hipStream_t stream) {
-  if (K == 0) K = 1;
-  if (waves <= 0) waves = 4;
-  const int tile = kWave * K;
-  const int n_tiles = (B + tile - 1) / tile;
-  // enough workgroups to fill the chip; each takes consecutive tiles of a genome
-  const int want = std::max(1, std::min(n_tiles, (2048 + p.P - 1) / std::max(1, p.P)));
-  const int per_wg = (n_tiles + want - 1) / want;
-  const int n_groups = (n_tiles + per_wg - 1) / per_wg;
-  FwdArgs a{obs_stride, B, 0, 0.0f, 0.0f, n_tiles, n_groups, per_wg};
-  const int64_t grid = (int64_t)p.P * n_groups;
-  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
-  return dispatch<false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, K, waves, stream);
+                   int64_t obs_stride, int B, float* out, const LdsTile& tile,
+                   const FwdWork& work, hipStream_t stream) {
+  const int K = tile.K == 0 ? 1 : tile.K;
+  const int waves = tile.waves <= 0 ? 4 : tile.waves;
+  const int rows = tile.rows <= 0 || tile.rows > p.N_max ? p.N_max : tile.rows;
+  if (waves > 8) return TN_EINVAL;
+  const int n_list = work.genomes ? work.n_genomes : p.P;
+  const int ktile = kWave * K;
+  const int n_tiles = (B + ktile - 1) / ktile;
+  FwdArgs a{obs_stride, B,   0,     0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.skip_le,
+            work.genomes, work.queue, n_list};
+  int grid = work.grid;
+  if (!work.queue) {
+    // enough workgroups to fill the chip; each takes consecutive tiles of a genome
+    const int want = std::max(1, std::min(n_tiles, (2048 + n_list - 1) / std::max(1, n_list)));
+    a.per_wg = (n_tiles + want - 1) / want;
+    a.n_groups = (n_tiles + a.per_wg - 1) / a.per_wg;
+    const int64_t g64 = (int64_t)n_list * a.n_groups;
+    if (g64 > 0x7fffffff) return TN_EUNSUPPORTED;
+    grid = (int)g64;
+  }
+  return dispatch<false>(p, t, obs, out, nullptr, nullptr, a, grid, K, waves, stream);
 }
 
 int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
                         int64_t obs_stride, int B, const float* target, int64_t target_stride,
-                        float scale, float offset, float* out, float* loss, hipStream_t stream) {
+                        float scale, float offset, float* out, float* loss, int skip_le,
+                        hipStream_t stream) {
   const int n_tiles = (B + kWave - 1) / kWave;
-  FwdArgs a{obs_stride, B, target_stride, scale, offset, n_tiles, 1, n_tiles};
+  const int rows = std::min(p.N_max, lds_rows_cap(p));
+  FwdArgs a{obs_stride, B, target_stride, scale, offset, n_tiles, 1, n_tiles, rows, skip_le,
+            nullptr, nullptr, 0};
   return dispatch<true>(p, t, obs, out, target, loss, a, p.P, 1, 4, stream);
 }
 

@@ -1,0 +1,421 @@
+// Calculation stage (TensorNEAT Section 3.3) for genomes whose forward pass
+// needs at most 64 value rows, with every node value held in registers.
+//
+// Mapping: one wavefront per tile of 64 observations of one genome (lane =
+// observation); a workgroup holds W wavefronts of the same genome, so that the
+// genome's packed program (tn_transformed.prog_node / prog_edge) is fetched
+// into the compute unit's scalar cache once. The program is read with scalar
+// loads and every loop and branch over it is wavefront uniform. A lane's node
+// values live in one or two 32-entry register banks addressed with a uniform
+// index (s_set_gpr_idx), so an in-edge costs one indexed register read and one
+// fused multiply-add: no LDS traffic and no barrier in the evaluation. The
+// value rows are the packed program's rows (freed right after their last
+// read; input k sits in row k). Observations are read coalesced and transposed
+// through a small per-wavefront LDS buffer; outputs leave the same way.
+#include <algorithm>
+
+#include "fwd_core.hpp"
+#include "fwd_launch.hpp"
+
+namespace tn {
+
+namespace {
+
+typedef float f32x32 __attribute__((ext_vector_type(32)));
+
+// Node values of one lane: rows 0..31 in bank lo, rows 32..63 in bank hi
+// (NB = 2). The banks are plain local vectors (a struct around them makes the
+// compiler keep them in scratch memory).
+template <int NB>
+__device__ __forceinline__ float vget(const f32x32& lo, const f32x32& hi, int r) {
+  if (NB == 1) return lo[r];
+  const int r0 = r & 31;
+  const float a = lo[r0], b = hi[r0];
+  return r < 32 ? a : b;
+}
+
+// Both banks are written at r & 31, the untouched one with its own value: a
+// write under a branch would make the compiler copy the whole bank.
+template <int NB>
+__device__ __forceinline__ void vset(f32x32& lo, f32x32& hi, int r, float x) {
+  if (NB == 1) {
+    lo[r] = x;
+    return;
+  }
+  const int r0 = r & 31;
+  const float o0 = lo[r0], o1 = hi[r0];
+  lo[r0] = r < 32 ? x : o0;
+  hi[r0] = r < 32 ? o1 : x;
+}
+
+struct RegArgs {
+  int64_t obs_stride;
+  int B;
+  int64_t target_stride;
+  float scale, offset;
+  int n_tiles;     // tiles of 64 observations per genome
+  int n_groups;    // workgroups per list entry (grid form without loss)
+  int per_wave;    // consecutive tiles per wavefront (grid form without loss)
+  int rows;        // value rows in registers: 32 or 64
+  int rows_lo;     // genomes with prog_rows <= rows_lo are left to another launch (-1: none)
+  int skip_above;  // genomes needing more than `rows` rows are left to another launch
+  const int32_t* genomes;  // genome list (nullptr: every genome, in order)
+  int32_t* queue;          // persistent form: next item to take
+  int n_items;             // persistent form: list length * n_tiles
+};
+
+// Observations and outputs pass through LDS in chunks of up to kChunk
+// components per observation; a row of the chunk has an odd stride, so the
+// per-lane row accesses are free of bank conflicts.
+constexpr int kChunk = 32;
+constexpr int kStage = kWave * (kChunk + 1);  // floats per wavefront
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd;
+  const int full = per * kXcd;
+  if (bid >= full) return bid;
+  return (bid % kXcd) * per + bid / kXcd;
+}
+
+// Program row of (non-input) position p: bits 16..30 of its function word.
+__device__ __forceinline__ int prog_row(const int4* __restrict__ pn, int p) {
+  return (pn[p].y >> 16) & 0x7fff;
+}
+
+// In-edges e .. e1-1 of one position, aggregated (Section 3.3's f_agg).
+template <int NB>
+__device__ __forceinline__ float aggregate(const f32x32& lo, const f32x32& hi,
+                                           const int2* __restrict__ pe,
+                                           int& e, int e1, int agg) {
+  float s = 0.0f;
+  if (agg == TN_AGG_SUM) {
+    // scalar loads return out of order, so every use waits for all of them:
+    // groups of 8 edges (one s_load_dwordx16) amortise that wait
+    for (; e + 8 <= e1; e += 8) {
+      int2 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = pe[e + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = fmaf(__int_as_float(q[u].y), vget<NB>(lo, hi, q[u].x), s);
+    }
+    if (e + 4 <= e1) {
+      int2 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) q[u] = pe[e + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s = fmaf(__int_as_float(q[u].y), vget<NB>(lo, hi, q[u].x), s);
+      e += 4;
+    }
+    for (; e < e1; ++e) {
+      const int2 q = pe[e];
+      s = fmaf(__int_as_float(q.y), vget<NB>(lo, hi, q.x), s);
+    }
+    return s;
+  }
+  if (e == e1) return s;
+  const int e0 = e;
+  {
+    const int2 q = pe[e];
+    s = __int_as_float(q.y) * vget<NB>(lo, hi, q.x);
+  }
+  for (++e; e < e1; ++e) {
+    const int2 q = pe[e];
+    const float t = __int_as_float(q.y) * vget<NB>(lo, hi, q.x);
+    switch (agg) {
+      case TN_AGG_PRODUCT: s = s * t; break;
+      case TN_AGG_MAX: s = fmaxf(s, t); break;
+      case TN_AGG_MIN: s = fminf(s, t); break;
+      case TN_AGG_MEAN: s = s + t; break;
+      default: s = fabsf(t) > fabsf(s) ? t : s; break;  // maxabs
+    }
+  }
+  if (agg == TN_AGG_MEAN) s = s / (float)(e1 - e0);
+  return s;
+}
+
+// One tile of 64 observations: input rows from the staging buffer, program
+// walk, output rows back to the staging buffer, chunk by chunk.
+template <int NB, bool kLoss>
+__device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
+                                          const int2* __restrict__ pe,
+                                          const int32_t* __restrict__ out_pos, int orow_first,
+                                          int n, int I, int O, int nbat,
+                                          const float* __restrict__ xo, float* __restrict__ yo,
+                                          const float* __restrict__ to, float* stg, int lane) {
+  // The banks start at zero in every tile; the empty asm keeps the compiler
+  // from hoisting that out of the tile loop (which would keep both banks of
+  // every variant live across it).
+  f32x32 lo = 0.0f, hi = 0.0f;
+  asm volatile("" : "+v"(lo));
+  if (NB == 2) asm volatile("" : "+v"(hi));
+  // inputs: coalesced loads of the tile's rows, transposed through LDS
+  for (int c0 = 0; c0 < I; c0 += kChunk) {
+    const int ch = min(kChunk, I - c0);
+    const int sr = ch | 1;
+    const int tot = nbat * ch;
+    DivWalk dw(lane, ch, kWave);
+    for (int i0 = 0; i0 < tot; i0 += 8 * kWave) {
+      float t[8];
+      int o[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = i0 + u * kWave + lane < tot;
+        o[u] = ok ? dw.b * sr + dw.c : -1;
+        t[u] = ok ? xo[(int64_t)dw.b * I + c0 + dw.c] : 0.0f;
+        dw.step();
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (o[u] >= 0) stg[o[u]] = t[u];
+    }
+    wave_sync();
+    for (int j = 0; j < ch; ++j) vset<NB>(lo, hi, c0 + j, stg[lane * sr + j]);
+    wave_sync();
+  }
+  // the program, in topological order; the next position's header is loaded
+  // before this position's edges, so one wait covers both
+  int e = 0;
+  int4 h = pn[0];
+  for (int p = 0; p < n; ++p) {
+    const int4 nx = pn[p + 1 < n ? p + 1 : p];
+    const int f = h.y;
+    if (f >= 0) {  // an input's row already holds the observation
+      const float s = aggregate<NB>(lo, hi, pe, e, h.x, (f >> 8) & 0xff);
+      const float z[1] = {fmaf(__int_as_float(h.w), s, __int_as_float(h.z))};
+      float a[1];
+      activate_all<1>(f & 0xff, z, a);
+      vset<NB>(lo, hi, (f >> 16) & 0x7fff, a[0]);
+    }
+    h = nx;
+  }
+  // outputs
+  float sse = 0.0f;
+  for (int c0 = 0; c0 < O; c0 += kChunk) {
+    const int ch = min(kChunk, O - c0);
+    const int sr = ch | 1;
+    const int orow = c0 == 0 ? orow_first : (lane < ch ? prog_row(pn, out_pos[c0 + lane]) : 0);
+    for (int j = 0; j < ch; ++j) stg[lane * sr + j] = vget<NB>(lo, hi, __builtin_amdgcn_readlane(orow, j));
+    wave_sync();
+    const int tot = nbat * ch;
+    DivWalk dw(lane, ch, kWave);
+    for (int i = lane; i < tot; i += kWave) {
+      const float y = stg[dw.b * sr + dw.c];
+      const int64_t at = (int64_t)dw.b * O + c0 + dw.c;
+      if (yo) yo[at] = y;
+      if (kLoss) {
+        const float d = y - to[at];
+        sse = fmaf(d, d, sse);
+      }
+      dw.step();
+    }
+    wave_sync();
+  }
+  return sse;
+}
+
+#define TN_REG_PARAMS                                                                        \
+  PopView pop, const int32_t *__restrict__ status, const int32_t *__restrict__ prog_rows,     \
+      const int32_t *__restrict__ n_valid, const int4 *__restrict__ prog_node,               \
+      const int2 *__restrict__ prog_edge, const int32_t *__restrict__ io_pos,                \
+      const float *__restrict__ obs, float *__restrict__ out,                                \
+      const float *__restrict__ target, RegArgs a
+#define TN_REG_ARGS pop, status, prog_rows, n_valid, prog_node, prog_edge, io_pos, obs, out, target, a
+
+// Tiles t_begin, t_begin + t_step, ... < t_end of genome g by this wavefront;
+// returns its part of the squared error (kLoss). *st_out: the genome's
+// status as the launch sees it (0: evaluated; -2: left to another launch).
+// NB = 0 picks one or two register banks from the genome's prog_rows.
+template <int NB, bool kLoss>
+__device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, int t_end,
+                                            int t_step, float* stg, int* st_out) {
+  const int lane = lane_id();
+  const int I = pop.n_in, O = pop.n_out, nio = I + O;
+  const int rows = prog_rows[g];
+  if (rows <= a.rows_lo || (a.skip_above && rows > a.rows)) {
+    *st_out = -2;
+    return 0.0f;
+  }
+  // a flagged genome, or one needing more rows than the launch holds, is NaN
+  const int st = status[g] ? status[g] : (rows > a.rows ? -1 : 0);
+  *st_out = st;
+  const int n = n_valid[g];
+  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g);
+  const int4* pn = prog_node + nb;
+  const int2* pe = prog_edge + cb;
+  const int32_t* out_pos = io_pos + (int64_t)g * nio + I;
+  const int orow_first = !st && lane < min(O, kChunk) ? prog_row(pn, out_pos[lane]) : 0;
+  const bool one_bank = NB == 1 || (NB == 0 && rows <= 32);
+  float sse = 0.0f;
+  for (int t = t_begin; t < t_end; t += t_step) {
+    const int b0 = t * kWave;
+    const int nbat = min(kWave, a.B - b0);
+    float* yo = out ? out + ((int64_t)g * a.B + b0) * O : nullptr;
+    if (st) {
+      if (yo)
+        for (int i = lane; i < nbat * O; i += kWave) yo[i] = __builtin_nanf("");
+      continue;
+    }
+    const float* xo = obs + (int64_t)g * a.obs_stride + (int64_t)b0 * I;
+    const float* to = kLoss ? target + (int64_t)g * a.target_stride + (int64_t)b0 * O : nullptr;
+    if (one_bank)
+      sse += run_tile<1, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
+                                lane);
+    else
+      sse += run_tile<2, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
+                                lane);
+  }
+  return sse;
+}
+
+// Grid form: workgroups over (list entry, group of tiles); with kLoss one
+// workgroup per list entry whose wavefronts share its tiles and reduce the
+// squared error in a fixed order.
+template <int NB, bool kLoss>
+__global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
+                                                                float* __restrict__ loss) {
+  extern __shared__ __align__(16) float stage_all[];
+  __shared__ float part[8];
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int W = blockDim.x / kWave;
+  float* stg = stage_all + wave * kStage;
+  int item, t_begin, t_end, t_step;
+  if (kLoss) {
+    item = blockIdx.x;
+    t_begin = wave;
+    t_end = a.n_tiles;
+    t_step = W;
+  } else {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    item = b / a.n_groups;
+    t_begin = ((b - item * a.n_groups) * W + wave) * a.per_wave;
+    t_end = min(t_begin + a.per_wave, a.n_tiles);
+    t_step = 1;
+  }
+  const int g = a.genomes ? a.genomes[item] : item;
+  int st;
+  const float sse = reg_genome<NB, kLoss>(TN_REG_ARGS, g, t_begin, t_end, t_step, stg, &st);
+  if (kLoss && st != -2) {  // st is uniform over the workgroup
+    // deterministic: fixed per-thread assignment, fixed reduction order
+    const float total = wave_sum(sse);
+    if (lane == 0) part[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float acc = 0.0f;
+      for (int v = 0; v < W; ++v) acc += part[v];
+      loss[g] = st ? __builtin_nanf("") : fmaf(a.scale, acc, a.offset);
+    }
+  }
+}
+
+// Persistent form: every wavefront takes the next (list entry, tile) item from
+// a counter until the items are exhausted (list entries are ordered longest
+// first); the counter must be 0 at launch.
+template <int NB>
+__global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PARAMS) {
+  extern __shared__ __align__(16) float stage_all[];
+  const int lane = lane_id();
+  float* stg = stage_all + (threadIdx.x / kWave) * kStage;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(a.queue, 1);
+    item = __builtin_amdgcn_readfirstlane(item);  // uniform: keeps the program on scalar loads
+    if (item >= a.n_items) break;
+    const int e = item / a.n_tiles, t = item - e * a.n_tiles;
+    int st;
+    reg_genome<NB, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+  }
+}
+
+template <int NB, bool kLoss>
+int launch_grid(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
+                const float* target, float* loss, const RegArgs& a, int grid, int waves,
+                hipStream_t stream) {
+  if (grid == 0) return TN_OK;
+  const size_t lds = sizeof(float) * (size_t)kStage * waves;
+  hipLaunchKernelGGL((forward_reg_kernel<NB, kLoss>), dim3((unsigned)grid), dim3(kWave * waves),
+                     lds, stream, make_view(p), t.status, t.prog_rows, t.n_valid,
+                     reinterpret_cast<const int4*>(t.prog_node),
+                     reinterpret_cast<const int2*>(t.prog_edge), t.io_pos, obs, out, target, a,
+                     loss);
+  return check_launch();
+}
+
+template <int NB>
+int launch_queue(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
+                 const RegArgs& a, int grid, int waves, hipStream_t stream) {
+  if (grid == 0) return TN_OK;
+  const size_t lds = sizeof(float) * (size_t)kStage * waves;
+  hipLaunchKernelGGL((forward_reg_queue_kernel<NB>), dim3((unsigned)grid), dim3(kWave * waves),
+                     lds, stream, make_view(p), t.status, t.prog_rows, t.n_valid,
+                     reinterpret_cast<const int4*>(t.prog_node),
+                     reinterpret_cast<const int2*>(t.prog_edge), t.io_pos, obs, out,
+                     (const float*)nullptr, a);
+  return check_launch();
+}
+
+}  // namespace
+
+int launch_forward_reg(const tn_population& p, const tn_transformed& t, const float* obs,
+                       int64_t obs_stride, int B, float* out, const RegTile& tile,
+                       const FwdWork& work, hipStream_t stream) {
+  const int waves = tile.waves <= 0 ? 4 : tile.waves;
+  const int rows = tile.rows <= 0 ? 64 : tile.rows;
+  if (waves > 8 || (rows != 32 && rows != 64) || tile.banks < 0 || tile.banks > 2 ||
+      (tile.banks == 1 && rows != 32))
+    return TN_EINVAL;
+  const int n_list = work.genomes ? work.n_genomes : p.P;
+  const int n_tiles = (B + kWave - 1) / kWave;
+  RegArgs a{obs_stride, B,  0, 0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.rows_lo,
+            tile.skip_above ? 1 : 0, work.genomes, work.queue, 0};
+  if (work.queue) {
+    a.n_items = n_list * n_tiles;
+    switch (tile.banks) {
+      case 1: return launch_queue<1>(p, t, obs, out, a, work.grid, waves, stream);
+      case 2: return launch_queue<2>(p, t, obs, out, a, work.grid, waves, stream);
+      default: return launch_queue<0>(p, t, obs, out, a, work.grid, waves, stream);
+    }
+  }
+  // enough wavefronts to fill the chip; each takes consecutive tiles of a genome
+  const int want = std::max(1, std::min(n_tiles, (8192 + n_list - 1) / std::max(1, n_list)));
+  a.per_wave = (n_tiles + want - 1) / want;
+  const int waves_needed = (n_tiles + a.per_wave - 1) / a.per_wave;
+  a.n_groups = (waves_needed + waves - 1) / waves;
+  const int64_t grid = (int64_t)n_list * a.n_groups;
+  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
+  switch (tile.banks) {
+    case 1: return launch_grid<1, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
+    case 2: return launch_grid<2, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
+    default: return launch_grid<0, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
+  }
+}
+
+int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, const float* obs,
+                            int64_t obs_stride, int B, const float* target,
+                            int64_t target_stride, float scale, float offset, float* out,
+                            float* loss, int waves, bool skip_above, hipStream_t stream) {
+  if (waves <= 0) waves = 4;
+  if (waves > 8) return TN_EINVAL;
+  const int n_tiles = (B + kWave - 1) / kWave;
+  RegArgs a{obs_stride, B,  target_stride, scale,   offset, n_tiles, 1, n_tiles, 64, -1,
+            skip_above ? 1 : 0, nullptr, nullptr, 0};
+  return launch_grid<0, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
+}
+
+int reg_queue_grid(int banks, int waves) {
+  int dev = 0, cus = 0, per_cu = 0;
+  const size_t lds = sizeof(float) * kStage * waves;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) {
+    const void* k = banks == 1   ? (const void*)forward_reg_queue_kernel<1>
+                    : banks == 2 ? (const void*)forward_reg_queue_kernel<2>
+                                 : (const void*)forward_reg_queue_kernel<0>;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWave * waves, lds);
+  }
+  if (record_hip(e) != TN_OK) return 0;
+  return std::max(1, per_cu) * cus;
+}
+
+}  // namespace tn

@@ -128,14 +128,19 @@ __device__ __forceinline__ void activate_all(int act, const float (&z)[K], float
 // One topological position of a genome's program.
 struct NodeRec {
   int32_t erange;  // first in-edge | one-past-last in-edge << 16
-  int32_t fn;      // act | agg << 8; negative for an input position
+  int32_t fn;      // act | agg << 8 | value row << 16; negative for an input position
   float bias;
   float resp;
 };
 struct EdgeRec {
-  int32_t src;  // topological position of the source
+  int32_t src;  // value row of the source
   float w;
 };
+
+// Node function word of a non-input position with its value row attached.
+__host__ __device__ __forceinline__ int32_t fn_with_row(int32_t fn, int32_t row) {
+  return fn < 0 ? fn : ((fn & 0xffff) | (row << 16));
+}
 
 // Program staged in LDS (one copy per workgroup).
 struct LdsProg {
@@ -155,26 +160,27 @@ struct GlobalProg {
   const int32_t* resp;
   const int32_t* src;
   const int32_t* w;
+  const int32_t* row;  // value row of each position
   __device__ __forceinline__ NodeRec node(int p) const {
     NodeRec r;
     r.erange = rp[p] | (rp[p + 1] << 16);
-    r.fn = fn[p];
+    r.fn = fn_with_row(fn[p], row[p]);
     r.bias = __int_as_float(bias[p]);
     r.resp = __int_as_float(resp[p]);
     return r;
   }
   __device__ __forceinline__ EdgeRec edge(int e) const {
     EdgeRec q;
-    q.src = src[e];
+    q.src = row[src[e]];
     q.w = __int_as_float(w[e]);
     return q;
   }
 };
 
 // Evaluates position p of the program for this lane's K observations, whose
-// floats sit at mine + row * kRow. Inputs are skipped (their rows hold the
-// observation). Sum aggregation accumulates in ascending in-edge order with
-// fused multiply-add.
+// floats sit at mine + row * kRow (value rows come from the program). Inputs
+// are skipped (their rows hold the observation). Sum aggregation accumulates
+// in ascending in-edge order with fused multiply-add.
 template <int K, int kRow, class Prog>
 __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) {
   const NodeRec rec = prog.node(p);
@@ -251,7 +257,7 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
   Vec<K> out;
 #pragma unroll
   for (int k = 0; k < K; ++k) out.x[k] = v[k];
-  out.store(mine + p * kRow);
+  out.store(mine + ((f >> 16) & 0x7fff) * kRow);
 }
 
 }  // namespace tn

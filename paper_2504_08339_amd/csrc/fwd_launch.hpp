@@ -1,0 +1,58 @@
+// Host-side launchers of the forward kernels, shared by the C entry points and
+// the batched plan.
+#pragma once
+
+#include "tn_internal.hpp"
+
+namespace tn {
+
+// Where a launch's genomes come from.
+struct FwdWork {
+  const int32_t* genomes = nullptr;  // device list of genome indices (nullptr: all P, in order)
+  int n_genomes = 0;                 // list length
+  int32_t* queue = nullptr;          // persistent form: device counter, 0 at launch
+  int grid = 0;                      // persistent form: workgroups
+};
+
+// Register engine (forward_reg.hip).
+struct RegTile {
+  int waves = 4;            // wavefronts per workgroup (1..8)
+  int rows = 64;            // 32 or 64 value rows in registers
+  int banks = 0;            // 1 or 2 register banks; 0: chosen per genome
+  int rows_lo = -1;         // genomes with prog_rows <= rows_lo are skipped
+  bool skip_above = false;  // genomes with prog_rows > rows are skipped (else NaN)
+};
+
+// Level-parallel LDS engine (forward.hip).
+struct LdsTile {
+  int K = 1;          // observations per lane (1, 2, 4)
+  int waves = 4;      // wavefronts per workgroup (1..8)
+  int rows = 0;       // value rows per tile (0: N_max)
+  int skip_le = -1;   // genomes with prog_rows <= skip_le are skipped
+};
+
+int launch_forward_reg(const tn_population& p, const tn_transformed& t, const float* obs,
+                       int64_t obs_stride, int B, float* out, const RegTile& tile,
+                       const FwdWork& work, hipStream_t stream);
+int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, const float* obs,
+                            int64_t obs_stride, int B, const float* target,
+                            int64_t target_stride, float scale, float offset, float* out,
+                            float* loss, int waves, bool skip_above, hipStream_t stream);
+// Resident workgroups (whole device) of the persistent register kernel.
+int reg_queue_grid(int banks, int waves);
+
+int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
+                   int64_t obs_stride, int B, float* out, const LdsTile& tile,
+                   const FwdWork& work, hipStream_t stream);
+int launch_forward_loss(const tn_population& p, const tn_transformed& t, const float* obs,
+                        int64_t obs_stride, int B, const float* target, int64_t target_stride,
+                        float scale, float offset, float* out, float* loss, int skip_le,
+                        hipStream_t stream);
+// Largest row count the LDS engine holds at one observation per lane.
+int lds_rows_cap(const tn_population& p);
+// LDS bytes of one workgroup of the LDS engine (0 if the tile does not fit).
+size_t lds_tile_bytes(const tn_population& p, int K, int rows);
+// Resident workgroups (whole device) of the persistent LDS kernel.
+int lds_queue_grid(const tn_population& p, int K, int waves, int rows);
+
+}  // namespace tn

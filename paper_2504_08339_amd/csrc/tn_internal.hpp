@@ -58,6 +58,11 @@ struct TrView {
   float* pos_resp;
   int32_t* pos_fn;
   int32_t* io_pos;
+  int32_t* pos_row;
+  int32_t* n_rows;
+  int4* prog_node;
+  int2* prog_edge;
+  int32_t* prog_rows;
 };
 
 inline PopView make_view(const tn_population& p) {
@@ -75,7 +80,10 @@ inline TrView make_view(const tn_transformed& t) {
   v.status = t.status; v.n_valid = t.n_valid; v.order = t.order; v.level = t.level;
   v.row_ptr = t.row_ptr; v.edge_src = t.edge_src; v.edge_row = t.edge_row;
   v.edge_w = t.edge_w; v.pos_bias = t.pos_bias; v.pos_resp = t.pos_resp;
-  v.pos_fn = t.pos_fn; v.io_pos = t.io_pos;
+  v.pos_fn = t.pos_fn; v.io_pos = t.io_pos; v.pos_row = t.pos_row; v.n_rows = t.n_rows;
+  v.prog_node = reinterpret_cast<int4*>(t.prog_node);
+  v.prog_edge = reinterpret_cast<int2*>(t.prog_edge);
+  v.prog_rows = t.prog_rows;
   return v;
 }
 
@@ -107,6 +115,16 @@ __device__ __forceinline__ int wave_inclusive_scan(int x) {
   for (int off = 1; off < kWave; off <<= 1) {
     int t = __shfl_up(x, off, kWave);
     if (lane >= off) x += t;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_inclusive_max(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int t = __shfl_up(x, off, kWave);
+    if (lane >= off) x = max(x, t);
   }
   return x;
 }
@@ -151,6 +169,11 @@ int record_hip(hipError_t e);
 
 // Error of the launch just issued (hipGetLastError), recorded.
 inline int check_launch() { return record_hip(hipGetLastError()); }
+
+// Argument checks shared by the entry points (TN_OK or the error code).
+int check_population(const tn_population* p);
+int check_transformed(const tn_transformed* t);
+int check_obs(const tn_population* p, const float* obs, int64_t stride, int32_t B);
 
 // Lets `kernel` take `bytes` of dynamic LDS. Only requests above 64 KiB need
 // the function attribute; returns TN_EUNSUPPORTED beyond the device limit.

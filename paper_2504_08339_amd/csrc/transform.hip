@@ -12,6 +12,15 @@
 //   4. in-edge lists grouped by destination position: rows are dropped into
 //      buckets with LDS atomics, then each edge computes its rank among the
 //      bucket's rows, which makes the result independent of atomic order.
+//   5. value-row assignment for the forward pass: input k takes row k; then,
+//      level by level, every non-input position takes the lowest free row (or a
+//      new one), and after the level the rows of positions whose last consumer
+//      is in that level are freed (outputs keep theirs). A row freed in level L
+//      is only reused from level L+1 on, so the positions of one level can be
+//      evaluated concurrently.
+#include <algorithm>
+#include <climits>
+
 #include "tn_internal.hpp"
 
 namespace tn {
@@ -38,7 +47,7 @@ struct Layout {
   int HN, HC;              // hash table sizes (powers of two)
   int off_hkey, off_hslot, off_nkey, off_deg, off_rem, off_outdeg, off_pos,
       off_order, off_level, off_ptr, off_cursor, off_outlist, off_esrc, off_edst,
-      off_tmp, off_chash;
+      off_tmp, off_chash, off_csr_row;
   size_t bytes;
 };
 
@@ -58,7 +67,8 @@ Layout make_layout(int N, int C) {
     o += (bytes + 15) & ~size_t(15);
     return (int)at;
   };
-  L.off_chash = take(sizeof(unsigned long long) * L.HC);  // 8-byte aligned first
+  // 8-byte aligned first; reused for the free-event list of step 9b
+  L.off_chash = take(std::max(sizeof(unsigned long long) * L.HC, sizeof(int16_t) * (2 * N + C)));
   L.off_hkey = take(sizeof(int32_t) * L.HN);
   L.off_hslot = take(sizeof(int16_t) * L.HN);
   L.off_nkey = take(sizeof(int32_t) * N);
@@ -74,6 +84,7 @@ Layout make_layout(int N, int C) {
   L.off_esrc = take(sizeof(int16_t) * C);
   L.off_edst = take(sizeof(int16_t) * C);
   L.off_tmp = take(sizeof(int16_t) * C);
+  L.off_csr_row = take(sizeof(int16_t) * C);
   L.bytes = o;
   return L;
 }
@@ -100,18 +111,23 @@ __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int s
     tr.pos_bias[nb + p] = 0.0f;
     tr.pos_resp[nb + p] = 0.0f;
     tr.pos_fn[nb + p] = 0;
+    tr.pos_row[nb + p] = -1;
+    tr.prog_node[nb + p] = make_int4(0, 0, 0, 0);
   }
   for (int64_t p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = 0;
   for (int64_t e = lane; e < crows; e += kWave) {
     tr.edge_src[cb + e] = -1;
     tr.edge_row[cb + e] = -1;
     tr.edge_w[cb + e] = 0.0f;
+    tr.prog_edge[cb + e] = make_int2(0, 0);
   }
   const int nio = pop.n_in + pop.n_out;
   for (int k = lane; k < nio; k += kWave) tr.io_pos[(int64_t)g * nio + k] = -1;
   if (lane == 0) {
     tr.status[g] = st;
     tr.n_valid[g] = 0;
+    tr.n_rows[g] = 0;
+    tr.prog_rows[g] = 0;
   }
 }
 
@@ -150,6 +166,8 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   int16_t* esrc = (int16_t*)(smem + L.off_esrc);
   int16_t* edst = (int16_t*)(smem + L.off_edst);
   int16_t* tmp = (int16_t*)(smem + L.off_tmp);
+  int16_t* csr_row = (int16_t*)(smem + L.off_csr_row);  // connection row of CSR entry e
+  int16_t* csr_src = outlist;                              // source position of entry e
 
   for (int i = lane; i < L.HN; i += kWave) hkey[i] = kEmptyKey;
   for (int i = lane; i < L.HC; i += kWave) chash[i] = kEmptyMark;
@@ -317,6 +335,8 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
     tr.edge_row[o] = r;
     tr.edge_src[o] = pos_of[esrc[r]];
     tr.edge_w[o] = pop.conn_w[cb + r];
+    csr_row[lo + rank] = (int16_t)r;
+    csr_src[lo + rank] = pos_of[esrc[r]];
   }
   for (int e = n_edges + lane; e < crows; e += kWave) {
     tr.edge_row[cb + e] = -1;
@@ -348,9 +368,194 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   }
   for (int k = lane; k < nio; k += kWave)
     tr.io_pos[(int64_t)g * nio + k] = pos_of[lookup_node(hkey, hslot, L.HN, k)];
+
+  // 9. value rows with reuse (see the header). last[s]: position of the last
+  // consumer of s (-1: none; outputs never free their row).
+  __shared__ uint32_t free_bits[TN_MAX_NODES / 32];
+  __shared__ int next_row;
+  int32_t* last = deg;  // both are free now
+  int32_t* row = rem;
+  for (int p = lane; p < n_valid; p += kWave) last[p] = -1;
+  for (int w = lane; w < TN_MAX_NODES / 32; w += kWave) free_bits[w] = 0u;
+  wave_sync();
+  for (int p = lane; p < n_valid; p += kWave)
+    for (int j = ptr[p]; j < ptr[p + 1]; ++j) atomicMax(&last[csr_src[j]], p);
+  wave_sync();
+  // input k takes row k; an input nobody reads is free at once
+  for (int p = lane; p < n_valid; p += kWave) {
+    const int k = nkey[order_l[p]];
+    if (k < pop.n_in) {
+      row[p] = k;
+      if (last[p] < 0) atomicOr(&free_bits[k >> 5], 1u << (k & 31));
+    }
+  }
+  if (lane == 0) next_row = pop.n_in;
+  wave_sync();
+  for (int lb = 0; lb < n_valid;) {
+    const int lvl_here = level_l[lb];
+    int le = lb + 1;
+    while (le < n_valid && level_l[le] == lvl_here) ++le;  // uniform scan
+    // allocate the level's non-input positions, in order
+    for (int base = lb; base < le; base += kWave) {
+      const int p = base + lane;
+      const bool node = p < le && nkey[order_l[p]] >= pop.n_in;
+      const uint64_t m = __ballot(node);
+      const int k = __popcll(m);
+      if (k == 0) continue;
+      const int i = mbcnt(m);
+      // free rows available
+      int nfree = 0;
+      for (int w = 0; w < TN_MAX_NODES / 32; ++w) nfree += __popc(free_bits[w]);
+      if (node) {
+        int r;
+        if (i < nfree) {
+          int skip = i, w = 0;
+          while (__popc(free_bits[w]) <= skip) skip -= __popc(free_bits[w++]);
+          uint32_t x = free_bits[w];
+          for (int t = 0; t < skip; ++t) x &= x - 1;
+          r = w * 32 + (__ffs(x) - 1);
+        } else {
+          r = next_row + (i - nfree);
+        }
+        row[p] = r;
+      }
+      wave_sync();
+      if (node && i < nfree) atomicAnd(&free_bits[row[p] >> 5], ~(1u << (row[p] & 31)));
+      if (lane == 0 && k > nfree) next_row += k - nfree;
+      wave_sync();
+    }
+    // free the rows whose last consumer sits in this level, and those of this
+    // level's positions that nothing reads
+    for (int q = lane; q < n_valid; q += kWave) {
+      const int key = nkey[order_l[q]];
+      const bool is_out = key >= pop.n_in && key < pop.n_in + pop.n_out;
+      const bool dead_here = last[q] < 0 && key >= pop.n_in && q >= lb && q < le;
+      if (!is_out && ((last[q] >= lb && last[q] < le) || dead_here))
+        atomicOr(&free_bits[row[q] >> 5], 1u << (row[q] & 31));
+    }
+    wave_sync();
+    lb = le;
+  }
+  for (int p = lane; p < nrows; p += kWave) tr.pos_row[nb + p] = p < n_valid ? row[p] : -1;
+  wave_sync();
+
+  // 9b. value rows of the packed program, which is evaluated one position
+  // after the other: a value's row is free as soon as its last consumer has
+  // read it (that consumer may take it for its own result). Any reuse policy
+  // then needs the fewest rows, the largest number of values live at once.
+  // The one used serves allocations from freed rows in the order they were
+  // freed (first in, first out), so the u-th allocation served from freed rows
+  // takes the u-th freed row, and allocation needs only prefix sums and one
+  // prefix maximum: with F(p) the rows freed up to position p and A(p) the
+  // non-input positions up to p, the rows created up to p are
+  // max(0, max_{q <= p} A(q) - F(q)).
+  // Free events, in order: the unused inputs (at position 0); then at each
+  // position p the dead value at p-1 (a hidden node nobody reads), followed by
+  // the sources whose last consumer is p, in in-edge order. Outputs keep their
+  // rows.
+  int32_t* fcum = outdeg;                        // F(p)
+  int32_t* seq = cursor;                         // row, or -(s+1): the row of position s
+  int16_t* ev = (int16_t*)(smem + L.off_chash);  // position whose row the u-th event frees
+  int n_unused = 0;
+  for (int base = 0; base < n_valid; base += kWave) {
+    const int p = base + lane;
+    const bool un = p < n_valid && nkey[order_l[p]] < pop.n_in && last[p] < 0;
+    const uint64_t m = __ballot(un);
+    if (un) ev[n_unused + mbcnt(m)] = (int16_t)p;
+    n_unused += __popcll(m);
+  }
+  {
+    int carry = n_unused;
+    for (int base = 0; base < n_valid; base += kWave) {
+      const int p = base + lane;
+      int c = 0;
+      if (p < n_valid) {
+        if (p > 0) c += nkey[order_l[p - 1]] >= nio && last[p - 1] < 0;
+        for (int j = ptr[p]; j < ptr[p + 1]; ++j) {
+          const int s = csr_src[j];
+          const int ks = nkey[order_l[s]];
+          c += last[s] == p && !(ks >= pop.n_in && ks < nio);
+        }
+      }
+      const int incl = wave_inclusive_scan(c);
+      if (p < n_valid) fcum[p] = carry + incl;
+      carry += __shfl(incl, kWave - 1, kWave);
+    }
+  }
+  wave_sync();
+  for (int p = 1 + lane; p < n_valid; p += kWave) {
+    int i = fcum[p - 1];
+    if (nkey[order_l[p - 1]] >= nio && last[p - 1] < 0) ev[i++] = (int16_t)(p - 1);
+    for (int j = ptr[p]; j < ptr[p + 1]; ++j) {
+      const int s = csr_src[j];
+      const int ks = nkey[order_l[s]];
+      if (last[s] == p && !(ks >= pop.n_in && ks < nio)) ev[i++] = (int16_t)s;
+    }
+  }
+  wave_sync();
+  int n_new = 0;  // rows created so far (beyond the n_in input rows)
+  {
+    int a_carry = 0;
+    for (int base = 0; base < n_valid; base += kWave) {
+      const int p = base + lane;
+      const int k = p < n_valid ? nkey[order_l[p]] : 0;
+      const bool node = p < n_valid && k >= pop.n_in;
+      const int a = a_carry + wave_inclusive_scan(node ? 1 : 0);
+      const int d = node ? a - fcum[p] : INT_MIN;
+      const int nn = max(n_new, wave_inclusive_max(d));
+      int prev = __shfl_up(nn, 1, kWave);
+      if (lane == 0) prev = n_new;
+      if (p < n_valid) {
+        if (!node)
+          seq[p] = k;
+        else if (nn > prev)
+          seq[p] = pop.n_in + nn - 1;
+        else
+          seq[p] = -(ev[a - nn - 1] + 1);
+      }
+      a_carry = __shfl(a, kWave - 1, kWave);
+      n_new = __shfl(nn, kWave - 1, kWave);
+    }
+  }
+  wave_sync();
+  // resolve "same row as position s" links by pointer jumping (s < p always)
+  for (;;) {
+    bool more = false;
+    for (int p = lane; p < n_valid; p += kWave) {
+      const int v = seq[p];
+      if (v < 0) {
+        const int t = seq[-v - 1];
+        seq[p] = t;
+        more |= t < 0;
+      }
+    }
+    wave_sync();
+    if (__ballot(more) == 0) break;
+  }
+
+  // 10. packed program of the forward pass
+  for (int p = lane; p < nrows; p += kWave) {
+    int4 q = make_int4(0, 0, 0, 0);
+    if (p < n_valid) {
+      const int s = order_l[p];
+      const int k = nkey[s];
+      int32_t fn = (int32_t)((uint32_t)pop.node_act[nb + s] | ((uint32_t)pop.node_agg[nb + s] << 8));
+      fn = k < pop.n_in ? (int32_t)(kFnInput | ((uint32_t)k << 16)) : (fn | (seq[p] << 16));
+      q = make_int4(ptr[p + 1], fn, __float_as_int(pop.node_bias[nb + s]),
+                    __float_as_int(pop.node_resp[nb + s]));
+    }
+    tr.prog_node[nb + p] = q;
+  }
+  for (int e = lane; e < crows; e += kWave) {
+    int2 q = make_int2(0, 0);
+    if (e < n_edges) q = make_int2(seq[csr_src[e]], __float_as_int(pop.conn_w[cb + csr_row[e]]));
+    tr.prog_edge[cb + e] = q;
+  }
   if (lane == 0) {
     tr.status[g] = 0;
     tr.n_valid[g] = n_valid;
+    tr.n_rows[g] = next_row;
+    tr.prog_rows[g] = pop.n_in + n_new;
   }
 }
 

@@ -130,6 +130,31 @@ def test_calls_reject_bad_arguments_without_a_gpu(lib):
     assert lib.tn_forward(ctypes.byref(p), ctypes.byref(tr), obs, 0, 0, None, None) == _abi.TN_OK
 
 
+def test_tile_and_plan_calls_reject_bad_arguments_without_a_gpu(lib):
+    p = _fake_pop()
+    tr = _abi.TnTransformed()
+    obs = ctypes.cast(ctypes.c_void_p(0x4000), _abi.c_float_p)
+    for tile in ((7, 1, 4, 0), (_abi.TN_ENGINE_REG, 1, 4, 48), (_abi.TN_ENGINE_REG, 2, 4, 64),
+                 (_abi.TN_ENGINE_LDS, 3, 4, 0), (_abi.TN_ENGINE_LDS, 1, 9, 0),
+                 (_abi.TN_ENGINE_LDS, 1, 4, -1)):
+        t = _abi.TnTile(*tile)
+        assert lib.tn_forward_tiled(ctypes.byref(p), ctypes.byref(tr), obs, 0, 4, None,
+                                    ctypes.byref(t), None) == _abi.TN_EINVAL, tile
+    h = ctypes.c_void_p()
+    assert lib.tn_plan_create(ctypes.byref(p), ctypes.byref(tr), 4, None, None, None) == _abi.TN_EINVAL
+    assert lib.tn_plan_create(ctypes.byref(p), ctypes.byref(tr), 4, None, ctypes.byref(h),
+                              None) == _abi.TN_EINVAL       # transformed arrays missing
+    assert not h.value
+    assert lib.tn_plan_num_buckets(None) == 0
+    info = _abi.TnBucketInfo()
+    assert lib.tn_plan_bucket(None, 0, ctypes.byref(info)) == _abi.TN_EINVAL
+    assert lib.tn_plan_set_tile(None, 0, 1, 4) == _abi.TN_EINVAL
+    for name in ("tn_plan_forward", "tn_plan_forward_buckets"):
+        assert getattr(lib, name)(None, obs, 0, None, None) == _abi.TN_EINVAL
+    assert lib.tn_plan_tune(None, obs, 0, None, None, None) == _abi.TN_EINVAL
+    lib.tn_plan_destroy(None)
+
+
 def test_status_strings(lib):
     for code in range(6):
         assert lib.tn_status_string(code).startswith(b"TN_")

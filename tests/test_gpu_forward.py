@@ -181,3 +181,75 @@ def test_mse_loss_matches_oracle():
     for g in range(pop.P):
         ref = oracle.sse_loss(oracle.forward_population(pop, X, [g])[0], T, 1.0 / 2048)
         assert abs(loss[g] - ref) <= 1e-5 * abs(ref) + 1e-7
+
+
+@pytest.mark.parametrize("K,W", [(1, 1), (1, 4), (2, 4), (4, 2), (2, 8)])
+def test_lds_tile_shapes_and_tight_rows_bitwise(K, W):
+    """Every LDS tile shape, with rows sized to the population's largest n_rows,
+    gives the same bits as the default launch; too few rows gives NaN."""
+    import paper_2504_08339_amd as tn
+    pop = synth.control_population(P=80)
+    obs = synth.normal_obs(80, 300, 17, 7)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    xt = tensor(obs)
+    ref = host(tn.forward(dp, tr, xt))
+    rows = int(host(tr.n_rows).max())
+    assert rows < pop.N_max
+    lds = dict(engine=tn.TN_ENGINE_LDS, obs_per_lane=K, waves_per_genome=W)
+    y = host(tn.forward(dp, tr, xt, rows=rows, **lds))
+    assert np.array_equal(y.view(np.uint32), ref.view(np.uint32))
+    short = host(tn.forward(dp, tr, xt, rows=rows - 1, **lds))
+    need = host(tr.n_rows)[:pop.P]
+    assert np.isnan(short[need > rows - 1]).all()
+    assert np.array_equal(short[need <= rows - 1].view(np.uint32), ref[need <= rows - 1].view(np.uint32))
+
+
+@pytest.mark.parametrize("W,rows", [(1, 64), (4, 64), (8, 64), (4, 32), (2, 32)])
+def test_register_engine_bitwise_and_row_limit(W, rows):
+    """The register engine gives the LDS engine's bits for every genome whose
+    packed program fits its rows and NaN for the others; observations in one
+    shared batch and per genome, with a ragged last tile."""
+    import paper_2504_08339_amd as tn
+    pop = synth.control_population(P=90)
+    for obs in (synth.normal_obs(90, 333, 17, 8), synth.normal_obs(1, 333, 17, 9)[0]):
+        dp = to_device(pop)
+        tr = tn.transform(dp)
+        xt = tensor(obs)
+        ref = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_LDS, obs_per_lane=1,
+                              waves_per_genome=4))
+        y = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_REG, waves_per_genome=W, rows=rows))
+        need = host(tr.prog_rows)[:pop.P]
+        assert (need <= rows).any()
+        fit = need <= rows
+        assert np.array_equal(y[fit].view(np.uint32), ref[fit].view(np.uint32))
+        assert np.isnan(y[~fit]).all()
+
+
+@pytest.mark.parametrize("name", ["batching", "cppn", "differentiation"])
+def test_auto_split_equals_single_engine(name):
+    """The library's choice (registers for small programs, LDS for the rest)
+    gives the same bits as the LDS engine alone; checked against the oracle on
+    sampled genomes, and the fused loss on the same split."""
+    import paper_2504_08339_amd as tn
+    pop = {"batching": lambda: synth.batching_population(P=160),
+           "cppn": lambda: synth.cppn_population(P=160),
+           "differentiation": lambda: synth.differentiation_population(P=160)}[name]()
+    obs = synth.normal_obs(pop.P, 150, pop.n_in, 31)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    xt = tensor(obs)
+    auto = host(tn.forward(dp, tr, xt))
+    lds = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_LDS, obs_per_lane=1,
+                          waves_per_genome=2))
+    assert np.array_equal(auto.view(np.uint32), lds.view(np.uint32))
+    need = host(tr.prog_rows)[:pop.P]
+    if name == "batching":
+        assert (need <= 64).any() and (need > 64).any()
+    check(pop, obs, auto, list(range(0, pop.P, 9)))
+    T = np.random.default_rng(3).standard_normal((150, pop.n_out)).astype(np.float32)
+    loss, Y = tn.forward_loss(dp, tr, xt, tensor(T), scale=0.5, offset=1.0)
+    loss, Y = host(loss), host(Y)
+    assert np.array_equal(Y.view(np.uint32), auto.view(np.uint32))
+    ref = 1.0 + 0.5 * ((auto.astype(np.float64) - T) ** 2).sum(axis=(1, 2))
+    np.testing.assert_allclose(loss, ref, rtol=2e-5)

@@ -18,7 +18,8 @@ def run_transform(pop):
     tr = tn.transform(dp)
     return {k: host(getattr(tr, k)) for k in (
         "status", "n_valid", "order", "level", "row_ptr", "edge_src", "edge_row", "edge_w",
-        "pos_bias", "pos_resp", "pos_fn", "io_pos")}
+        "pos_bias", "pos_resp", "pos_fn", "io_pos", "pos_row", "n_rows", "prog_node",
+        "prog_edge", "prog_rows")}
 
 
 def blocks(pop, g):
@@ -148,3 +149,125 @@ def test_deterministic_reruns():
     b = run_transform(pop)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+
+
+def _check_rows(pop, got, g):
+    """Replays the level-by-level evaluation with the assigned value rows and
+    checks that no row is overwritten while a later level still reads it."""
+    ns, rb, cs = blocks(pop, g)
+    n = int(got["n_valid"][g])
+    order = got["order"][ns][:n]
+    level = got["level"][ns][:n]
+    row = got["pos_row"][ns][:n]
+    rp = got["row_ptr"][rb:rb + n + 1]
+    es = got["edge_src"][cs]
+    keys = pop.node_rows(g)["key"][order]
+    is_in = keys < pop.n_in
+    is_out = (keys >= pop.n_in) & (keys < pop.n_in + pop.n_out)
+    last_lvl = np.full(n, -1)
+    for p in range(n):
+        for e in range(rp[p], rp[p + 1]):
+            last_lvl[es[e]] = max(last_lvl[es[e]], level[p])
+    assert len(set(row[is_in].tolist())) == int(is_in.sum())
+    holder = {}                                   # row -> position currently holding it
+    for p in np.flatnonzero(is_in):
+        holder[row[p]] = p
+    for L in range(int(level.max()) + 1 if n else 0):
+        written = [p for p in range(n) if level[p] == L and not is_in[p]]
+        assert len({row[p] for p in written}) == len(written)
+        for p in written:
+            q = holder.get(row[p])
+            if q is not None:   # the previous holder must be dead before level L
+                assert not is_out[q]
+                assert last_lvl[q] < L, (g, p, q)
+            holder[row[p]] = p
+    for p in np.flatnonzero(is_out):
+        assert holder[row[p]] == p                # outputs survive to the end
+    assert int(got["n_rows"][g]) == (int(row.max()) + 1 if n else 0) <= n
+
+
+@pytest.mark.parametrize("name", ["control", "batching", "cppn"])
+def test_value_rows_reuse_is_safe(name):
+    pop = {"control": lambda: synth.control_population(P=300),
+           "batching": lambda: synth.batching_population(P=300),
+           "cppn": lambda: synth.cppn_population(P=300)}[name]()
+    got = run_transform(pop)
+    for g in range(pop.P):
+        _check_rows(pop, got, g)
+    rows = got["n_rows"][:pop.P]
+    nv = got["n_valid"][:pop.P]
+    assert (rows < nv).mean() > 0.5           # reuse actually saves rows
+
+
+def _check_prog(pop, got, g):
+    """The packed program of genome g: its fields mirror the position arrays,
+    and replaying it one position after the other never reads a row that was
+    overwritten; its row count is the largest number of values live at once."""
+    ns, rb, cs = blocks(pop, g)
+    n = int(got["n_valid"][g])
+    rp = got["row_ptr"][rb:rb + n + 1]
+    es = got["edge_src"][cs]
+    pn = got["prog_node"].reshape(-1, 4)[ns][:n]
+    pe = got["prog_edge"].reshape(-1, 2)[cs][:rp[n] if n else 0]
+    keys = pop.node_rows(g)["key"][got["order"][ns][:n]]
+    n_in, nio = pop.n_in, pop.n_in + pop.n_out
+    assert np.array_equal(pn[:, 0], rp[1:])
+    assert np.array_equal(pn[:, 2], got["pos_bias"][ns][:n].view(np.int32))
+    assert np.array_equal(pn[:, 3], got["pos_resp"][ns][:n].view(np.int32))
+    fn = got["pos_fn"][ns][:n]
+    inp = keys < n_in
+    assert np.array_equal(pn[inp, 1], fn[inp])
+    assert np.array_equal(pn[~inp, 1] & 0xffff, fn[~inp] & 0xffff)
+    prow = np.where(inp, keys, (pn[:, 1] >> 16) & 0x7fff)
+    assert np.array_equal(pe[:, 0], prow[es[:len(pe)]])
+    assert np.array_equal(pe[:, 1], got["edge_w"][cs][:len(pe)].view(np.int32))
+    last = np.full(n, -1)
+    for p in range(n):
+        for e in range(rp[p], rp[p + 1]):
+            last[es[e]] = max(last[es[e]], p)
+    holder = {int(k): p for p, k in enumerate(keys) if k < n_in}
+    live_max = n_in
+    for p in range(n):
+        if inp[p]:
+            continue
+        for e in range(rp[p], rp[p + 1]):
+            assert holder[int(pe[e, 0])] == es[e], (g, p, e)   # source still in its row
+        r = int(prow[p])
+        q = holder.get(r)
+        if q is not None:   # the row's previous value is dead from p on
+            assert not (n_in <= keys[q] < nio)
+            assert last[q] <= p, (g, p, q)
+        holder[r] = p
+        live = sum(1 for s in range(n) if (inp[s] and last[s] > p) or (
+            not inp[s] and s < p and ((n_in <= keys[s] < nio) or last[s] > p))) + 1
+        live_max = max(live_max, live)
+    for p in np.flatnonzero((keys >= n_in) & (keys < nio)):
+        assert holder[int(prow[p])] == p
+    assert int(got["prog_rows"][g]) == live_max
+    assert prow.max(initial=0) < live_max
+
+
+@pytest.mark.parametrize("name", ["control", "batching", "cppn"])
+def test_packed_program_rows(name):
+    pop = {"control": lambda: synth.control_population(P=200),
+           "batching": lambda: synth.batching_population(P=120),
+           "cppn": lambda: synth.cppn_population(P=200)}[name]()
+    got = run_transform(pop)
+    for g in range(pop.P):
+        if got["status"][g]:
+            assert got["prog_rows"][g] == 0
+            continue
+        _check_prog(pop, got, g)
+    # the program needs no more rows than the level-parallel assignment
+    ok = got["status"][:pop.P] == 0
+    assert np.all(got["prog_rows"][:pop.P][ok] <= got["n_rows"][:pop.P][ok])
+
+
+def test_packed_program_malformed_and_holed():
+    rng = np.random.default_rng(4)
+    for pop in (_malformed(), synth.insert_holes(synth.control_population(P=60), rng),
+                synth.permute_rows(synth.control_population(P=60), rng)):
+        got = run_transform(pop)
+        for g in range(pop.P):
+            if got["status"][g] == 0:
+                _check_prog(pop, got, g)
