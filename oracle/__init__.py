@@ -35,3 +35,4 @@ from .inference import (  # noqa: F401
 )
 from .compat import genome_genes, distance, distance_matrix  # noqa: F401
 from .adjoint import backward, backward_population  # noqa: F401
+from . import hyperneat  # noqa: F401
