@@ -358,6 +358,45 @@ int  tn_plan_forward_buckets(tn_plan* plan, const float* obs, int64_t obs_genome
 int  tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
                   const char* tune_cache, hipStream_t stream);
 
+/* ---------------------------------------------------------- HyperNEAT */
+
+/*
+ * HyperNEAT on a grid substrate (the indirect encoding among the library's
+ * algorithms, Section 4.4). A CPPN genome (5 inputs, 1 output) is queried for
+ * every substrate connection s -> t at (x_s, y_s, x_t, y_t, 1) with the
+ * forward rule above; |w| < threshold gives 0; the result is rounded to
+ * bfloat16 (round to nearest even). Geometry: the input and the hidden layer
+ * are grid x grid layers with node grid*r + c at (-1 + 2c/(grid-1),
+ * -1 + 2r/(grid-1)); output j of n_out sits at (-1 + 2j/(n_out-1), 0) (0 for
+ * n_out = 1). One CPPN gives both layers. The substrate has no biases:
+ *   H = tanh(X W1),  Y = bf16(H) W2
+ * with bfloat16 operands and float32 accumulation. S = grid*grid must be a
+ * multiple of 64 and S * n_out <= 32768 (TN_EUNSUPPORTED otherwise).
+ */
+typedef struct tn_substrate {
+    int32_t grid;
+    int32_t n_out;
+    float   threshold;
+} tn_substrate;
+
+/* Weights of every CPPN genome (pop->n_in must be 5, pop->n_out 1; tr from
+ * tn_transform on pop; every genome's prog_rows <= 64, else its weights are
+ * NaN, as are a flagged genome's). Outputs, bfloat16 bits, transposed so that
+ * rows run along the source index:
+ *   w1t [P][S][S]       w1t[g][t][s] = weight input s -> hidden t
+ *   w2t [P][n_out][S]   w2t[g][j][s] = weight hidden s -> output j
+ * raw1 / raw2 (NULL: not stored): the float32 CPPN values before the
+ * threshold, in the same layouts. */
+int tn_cppn_query(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,
+                  uint16_t* w1t, uint16_t* w2t, float* raw1, float* raw2, hipStream_t stream);
+
+/* Substrate forward of P genomes: x [B][S] bfloat16 bits per genome at
+ * x + g*x_genome_stride (0: shared); h [P][B][S] float32 (tanh of the fp32
+ * accumulation); y [P][B][n_out] float32, summed in ascending hidden index. */
+int tn_substrate_forward(const tn_substrate* sub, int32_t P, const uint16_t* w1t,
+                         const uint16_t* w2t, const uint16_t* x, int64_t x_genome_stride,
+                         int32_t B, float* h, float* y, hipStream_t stream);
+
 /* ---------------------------------------------------------- gradients */
 
 /*

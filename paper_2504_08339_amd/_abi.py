@@ -58,6 +58,10 @@ class TnTile(ctypes.Structure):
                 ("waves_per_genome", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
 
+class TnSubstrate(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("n_out", ctypes.c_int32), ("threshold", ctypes.c_float)]
+
+
 class TnBucketInfo(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("rows_class", ctypes.c_int32),
                 ("count", ctypes.c_int32), ("edges", ctypes.c_int64), ("tile", TnTile)]
@@ -104,6 +108,12 @@ SIGNATURES = {
                                                c_float_p, _STREAM]),
     "tn_plan_tune": (ctypes.c_int, [ctypes.c_void_p, c_float_p, ctypes.c_int64, c_float_p,
                                     ctypes.c_char_p, _STREAM]),
+    "tn_cppn_query": (ctypes.c_int, [_POP, _TR, ctypes.POINTER(TnSubstrate), ctypes.c_void_p,
+                                     ctypes.c_void_p, c_float_p, c_float_p, _STREAM]),
+    "tn_substrate_forward": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_int32, c_float_p, c_float_p,
+                                            _STREAM]),
 }
 
 

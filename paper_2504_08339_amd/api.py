@@ -307,3 +307,53 @@ class Plan:
         _check("tn_plan_tune", _lib.tn_plan_tune(
             self._h, _p(obs, _abi.c_float_p), stride, _p(out, _abi.c_float_p),
             tune_cache.encode() if tune_cache else None, _stream(self.pop.device)))
+
+
+def _substrate(grid: int, n_out: int, threshold: float):
+    return _abi.TnSubstrate(int(grid), int(n_out), float(threshold))
+
+
+def cppn_query(pop: Population, tr: Transformed, grid: int = 32, n_out: int = 8,
+               threshold: float = 0.2, raw: bool = False):
+    """(w1t [P][S][S], w2t [P][n_out][S]) bfloat16 substrate weights of every
+    CPPN genome (transposed: row = target), plus (raw1, raw2) float32 CPPN values
+    before the threshold when ``raw``."""
+    sub = _substrate(grid, n_out, threshold)
+    S = int(grid) * int(grid)
+    P, d = pop.P, pop.device
+    w1t = torch.empty((P, S, S), dtype=torch.bfloat16, device=d)
+    w2t = torch.empty((P, n_out, S), dtype=torch.bfloat16, device=d)
+    r1 = torch.empty((P, S, S), dtype=torch.float32, device=d) if raw else None
+    r2 = torch.empty((P, n_out, S), dtype=torch.float32, device=d) if raw else None
+    _check("tn_cppn_query", _lib.tn_cppn_query(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), ctypes.byref(sub),
+        ctypes.c_void_p(w1t.data_ptr()), ctypes.c_void_p(w2t.data_ptr()),
+        _p(r1, _abi.c_float_p), _p(r2, _abi.c_float_p), _stream(d)))
+    return (w1t, w2t, r1, r2) if raw else (w1t, w2t)
+
+
+def substrate_forward(w1t: torch.Tensor, w2t: torch.Tensor, x: torch.Tensor, grid: int = 32,
+                      n_out: int = 8, threshold: float = 0.2):
+    """(h [P][B][S] float32, y [P][B][n_out] float32) for bfloat16 inputs x
+    ([B][S] shared or [P][B][S])."""
+    if x.dtype != torch.bfloat16 or not x.is_contiguous():
+        raise TypeError("x must be a contiguous bfloat16 tensor")
+    for w in (w1t, w2t):
+        if w.dtype != torch.bfloat16 or not w.is_contiguous():
+            raise TypeError("weights must be contiguous bfloat16 tensors")
+    sub = _substrate(grid, n_out, threshold)
+    S = int(grid) * int(grid)
+    P = w1t.shape[0]
+    if x.dim() == 2:
+        B, stride = x.shape[0], 0
+    else:
+        B, stride = x.shape[1], x.shape[1] * x.shape[2]
+    if x.shape[-1] != S:
+        raise ValueError("x must have grid*grid columns")
+    h = torch.empty((P, B, S), dtype=torch.float32, device=x.device)
+    y = torch.empty((P, B, n_out), dtype=torch.float32, device=x.device)
+    _check("tn_substrate_forward", _lib.tn_substrate_forward(
+        ctypes.byref(sub), P, ctypes.c_void_p(w1t.data_ptr()), ctypes.c_void_p(w2t.data_ptr()),
+        ctypes.c_void_p(x.data_ptr()), stride, B, _p(h, _abi.c_float_p), _p(y, _abi.c_float_p),
+        _stream(x.device)))
+    return h, y

@@ -16,6 +16,13 @@ int launch_backward(const tn_population& p, const tn_transformed& t, const float
                     int64_t obs_stride, int B, const float* dY, int64_t dY_stride,
                     const float* target, int64_t target_stride, float scale, float* loss,
                     float* dW, float* db, hipStream_t stream);
+int check_substrate(const tn_substrate* sub);
+int launch_cppn_query(const tn_population& p, const tn_transformed& t, const tn_substrate& sub,
+                      uint16_t* w1t, uint16_t* w2t, float* raw1, float* raw2,
+                      hipStream_t stream);
+int launch_substrate_forward(const tn_substrate& sub, int P, const uint16_t* w1t,
+                             const uint16_t* w2t, const uint16_t* x, int64_t x_stride, int B,
+                             float* h, float* y, hipStream_t stream);
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
@@ -281,6 +288,33 @@ int tn_distance(const tn_population* pop, float c1, float c2, float c3, void* wo
   if (pop->P == 0) return TN_OK;
   if (!workspace || !dist) return TN_EINVAL;
   return launch_distance(*pop, c1, c2, c3, workspace, dist, excess, disjoint, stream);
+}
+
+int tn_cppn_query(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,
+                  uint16_t* w1t, uint16_t* w2t, float* raw1, float* raw2, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  if (pop->n_in != 5 || pop->n_out != 1) return TN_ESHAPE;
+  if (pop->P == 0) return TN_OK;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!w1t || !w2t) return TN_EINVAL;
+  return launch_cppn_query(*pop, *tr, *sub, w1t, w2t, raw1, raw2, stream);
+}
+
+int tn_substrate_forward(const tn_substrate* sub, int32_t P, const uint16_t* w1t,
+                         const uint16_t* w2t, const uint16_t* x, int64_t x_genome_stride,
+                         int32_t B, float* h, float* y, hipStream_t stream) {
+  int rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  if (P < 0 || B < 0 || x_genome_stride < 0) return TN_EINVAL;
+  const int64_t S = (int64_t)sub->grid * sub->grid;
+  if (x_genome_stride > 0 && x_genome_stride < (int64_t)B * S) return TN_ESHAPE;
+  if (P == 0 || B == 0) return TN_OK;
+  if (!w1t || !w2t || !x || !h || !y) return TN_EINVAL;
+  return launch_substrate_forward(*sub, P, w1t, w2t, x, x_genome_stride, B, h, y, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,194 @@
+"""GPU parity of the HyperNEAT path (tn_cppn_query, tn_substrate_forward)
+against the float64 oracle.
+
+CPPN values (before the threshold): the forward tolerance of test_gpu_forward,
+|w - w_ref| <= 1e-5 * cond + 2^-100. Stored weights: bit-exact round to
+nearest even of the GPU's own thresholded float32 value; threshold decisions
+equal the oracle's except where |w_ref| lies within the forward tolerance of
+the threshold (counted, not compared: both sides take the decision in their own
+precision there).
+Substrate: with the GPU's bfloat16 weights and inputs as exact float64 values
+(their products are exact in float32), float32 accumulation of K = 1024 terms
+errs by at most K * 2^-24 = 2^-14 times the sum of the terms' magnitudes, so
+|h - tanh(z_ref)| <= 2^-14 * sum_s |x_s w_s| + 2^-21 (the last term: tanh's
+own error from the hardware exp and reciprocal), and y against bf16(h) W2
+within 2^-14 * sum_t |bf16(h_t) w_t|. End to end against the float64 oracle
+with float64 weights (the GPU's threshold decisions): |y - y_ref| <= 2^-7 *
+error_scale: the four bfloat16 roundings take at most 2^-8 of it (pinned in
+test_oracle_hyperneat), the accumulations and the CPPN's float32 error (below
+1e-5 relative) stay inside the remaining factor of two.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import host, to_device
+from oracle import hyperneat as hn
+
+pytestmark = pytest.mark.gpu
+GRID, NOUT, THR = 32, 8, 0.2
+
+
+def _bf16_bits(x):
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    nan = np.isnan(np.asarray(x, np.float32))
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    r[nan] = 0x7FC0
+    return r
+
+
+def _bits16(t):
+    return host(t.view(torch.int16)).view(np.uint16)
+
+
+def _bf16_value(bits):
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _query(P, seed=5):
+    import paper_2504_08339_amd as tn
+    pop = synth.cppn_population(seed=seed, P=P)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, GRID, NOUT, THR, raw=True)
+    return tn, pop, dp, tr, w1t, w2t, r1, r2
+
+
+def _check_genome(pop, g, r1, r2, w1b, w2b):
+    gen = oracle.decode(pop, g)
+    tr = oracle.transform(gen)
+    grid, outs = hn.grid_coords(GRID), hn.row_coords(NOUT)
+    ambiguous = 0
+    for src_xy, dst_xy, raw, wb in ((grid, grid, r1[g], w1b[g]), (grid, outs, r2[g], w2b[g])):
+        ref, cond = oracle.forward(gen, tr, hn.query_inputs(src_xy, dst_xy), with_cond=True)
+        ref = ref[:, 0].reshape(len(src_xy), len(dst_xy)).T      # [t][s]
+        cond = cond[:, 0].reshape(len(src_xy), len(dst_xy)).T
+        tol = 1e-5 * cond + 2.0 ** -100
+        if tr.status:
+            assert np.isnan(raw).all()
+            continue
+        err = np.abs(raw.astype(np.float64) - ref)
+        assert np.all(err <= tol), (g, float(err.max()))
+        kept = np.where(np.abs(raw) < THR, np.float32(0), raw)
+        assert np.array_equal(wb, _bf16_bits(kept))
+        near = np.abs(np.abs(ref) - THR) <= tol
+        ambiguous += int(near.sum())
+        same = (np.abs(raw) < THR) == (np.abs(ref) < THR)
+        assert np.all(same | near)
+    return ambiguous
+
+
+def test_cppn_query_matches_oracle():
+    tn, pop, dp, tr, w1t, w2t, r1, r2 = _query(6)
+    r1, r2 = host(r1), host(r2)
+    w1b, w2b = _bits16(w1t), _bits16(w2t)
+    assert w1b.shape == (6, 1024, 1024) and w2b.shape == (6, 8, 1024)
+    amb = sum(_check_genome(pop, g, r1, r2, w1b, w2b) for g in range(pop.P))
+    print("threshold decisions within tolerance of 0.2:", amb)
+    assert (w1b != 0).any() and (w1b == 0).any()      # the threshold did something
+
+
+def test_cppn_query_flagged_and_shape_errors():
+    import paper_2504_08339_amd as tn
+    from helpers import population_from_rows
+    good = [[k, 0.0, 1.0, 0, 0] for k in range(5)] + [[5, 0.1, 1.0, 2, 0]]
+    cyc = good + [[7, 0.0, 1.0, 2, 0], [8, 0.0, 1.0, 2, 0]]
+    pop = population_from_rows([(good, [[0, 5, 1.0, 1], [4, 5, 0.5, 1]]),
+                                (cyc, [[7, 8, 1.0, 1], [8, 7, 1.0, 1], [8, 5, 1.0, 1]])], 5, 1,
+                               N_max=12, C_max=6)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, 8, 2, THR, raw=True)
+    assert host(tr.status)[1] != 0
+    assert np.isnan(host(r1)[1]).all() and np.all(_bits16(w1t)[1] == 0x7FC0)
+    assert np.isfinite(host(r1)[0]).all()
+    with pytest.raises(tn.TNError):
+        tn.cppn_query(dp, tr, 6, 2, THR)               # 36 nodes: not a multiple of 64
+    xor = to_device(synth.xor_population(P=2))
+    with pytest.raises(tn.TNError):
+        tn.cppn_query(xor, tn.transform(xor), 8, 2, THR)   # not a 5 -> 1 CPPN
+
+
+def _substrate_case(P, B, shared):
+    tn, pop, dp, tr, w1t, w2t = _query(P, seed=15)[:6]
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((B, GRID * GRID) if shared else (P, B, GRID * GRID)).astype(np.float32)
+    xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
+    return tn, pop, w1t, w2t, xb, host(h), host(y)
+
+
+@pytest.mark.parametrize("shared", [True, False])
+def test_substrate_forward_matches_oracle_on_gpu_weights(shared):
+    tn, pop, w1t, w2t, xb, h, y = _substrate_case(4, 100, shared)
+    W1 = _bf16_value(_bits16(w1t))          # [P][t][s]
+    W2 = _bf16_value(_bits16(w2t))          # [P][j][t]
+    Xv = _bf16_value(_bits16(xb))
+    for g in range(pop.P):
+        Xg = Xv if shared else Xv[g]
+        Z = Xg @ W1[g].T
+        S1 = np.abs(Xg) @ np.abs(W1[g]).T
+        assert np.all(np.abs(h[g] - np.tanh(Z)) <= 2.0 ** -14 * S1 + 2.0 ** -21), g
+        Hb = _bf16_value(_bf16_bits(h[g]))
+        ref = Hb @ W2[g].T
+        bound = 2.0 ** -14 * (np.abs(Hb) @ np.abs(W2[g]).T) + 1e-30
+        assert np.all(np.abs(y[g] - ref) <= bound), g
+
+
+def test_substrate_end_to_end_against_float64():
+    """GPU outputs against the float64 pipeline (float64 CPPN weights with the
+    GPU's threshold decisions, float64 inputs, no rounding)."""
+    tn, pop, dp, tr, w1t, w2t, r1, r2 = _query(3, seed=25)
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((64, GRID * GRID)).astype(np.float32)
+    xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
+    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
+    y = host(y)
+    r1, r2 = host(r1), host(r2)
+    grid, outs = hn.grid_coords(GRID), hn.row_coords(NOUT)
+    for g in range(pop.P):
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        raw1 = hn.cppn_weights(gen, otr, grid, grid)      # [s][t]
+        raw2 = hn.cppn_weights(gen, otr, grid, outs)
+        W1 = np.where(np.abs(r1[g].T) < THR, 0.0, raw1)   # the GPU's decisions
+        W2 = np.where(np.abs(r2[g].T) < THR, 0.0, raw2)
+        H, Y = hn.substrate_forward(X.astype(np.float64), W1, W2)
+        scale = hn.error_scale(X.astype(np.float64), W1, W2, H)
+        assert np.all(np.abs(y[g] - Y) <= 2.0 ** -7 * scale), g
+
+
+def test_full_size_sampled():
+    """1000 CPPNs on the 32 x 32 / 32 x 32 / 8 substrate with 128 inputs per
+    genome, as the benchmark runs it; two sampled genomes against the oracle."""
+    import paper_2504_08339_amd as tn
+    pop = synth.cppn_population()
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    w1t, w2t = tn.cppn_query(dp, tr, GRID, NOUT, THR)
+    X = torch.randn((pop.P, 128, GRID * GRID), generator=torch.Generator().manual_seed(5))
+    xb = X.cuda().to(torch.bfloat16)
+    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
+    torch.cuda.synchronize()
+    yh = host(y)
+    assert np.isfinite(yh).all()
+    W1 = w1t.float()
+    W2 = w2t.float()
+    Xv = xb.float()
+    for g in (17, 803):
+        ref = torch.tanh(Xv[g].double() @ W1[g].double().T)
+        assert torch.all((h[g].double() - ref).abs() <= 2.0 ** -14 * (Xv[g].double().abs() @ W1[g].double().abs().T) + 2.0 ** -21)
+        Hb = h[g].to(torch.bfloat16).double()
+        refy = Hb @ W2[g].double().T
+        assert torch.all((y[g].double() - refy).abs() <= 2.0 ** -14 * (Hb.abs() @ W2[g].double().abs().T) + 1e-30)
+        # the sampled weights against the oracle's CPPN
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        src = hn.grid_coords(GRID)[::97]
+        ref_w = hn.cppn_weights(gen, otr, src, hn.grid_coords(GRID))    # [s][t]
+        got = W1[g][:, ::97].cpu().numpy().T                          # [s][t]
+        ok = (np.abs(np.abs(ref_w) - THR) > 1e-4)
+        expect = _bf16_value(_bf16_bits(hn.threshold(ref_w).astype(np.float32)))
+        assert np.all((np.abs(got - expect) <= 2.0 ** -7 * np.abs(expect)) | ~ok)   # one bf16 step
