@@ -397,6 +397,23 @@ int tn_substrate_forward(const tn_substrate* sub, int32_t P, const uint16_t* w1t
                          const uint16_t* w2t, const uint16_t* x, int64_t x_genome_stride,
                          int32_t B, float* h, float* y, hipStream_t stream);
 
+/* Gradient of L = sum(dY * Y) through the substrate forward above, with
+ * respect to the weights as the forward used them (bfloat16 values):
+ *   dw2t [P][n_out][S]  dw2t[g][j][t] = sum_b H[b][t] dY[b][j]
+ *   dw1t [P][S][S]      dw1t[g][t][s] = sum_b dZ[b][t] x[b][s],
+ *                       dZ = (dY W2^T) (1 - H^2) rounded to bfloat16
+ * dy [P][B][n_out] float32; h the forward's output; w2t, x as given to the
+ * forward. float32 accumulation (dw2t in ascending b; dw1t on the matrix
+ * cores). workspace: tn_substrate_workspace_size bytes of device memory
+ * (caller-owned, contents irrelevant). n_out <= 32 and B * n_out <= 16384 here
+ * (TN_EUNSUPPORTED otherwise). */
+int tn_substrate_workspace_size(const tn_substrate* sub, int32_t P, int32_t B,
+                                int64_t x_genome_stride, size_t* bytes);
+int tn_substrate_backward(const tn_substrate* sub, int32_t P, const uint16_t* w2t,
+                          const uint16_t* x, int64_t x_genome_stride, int32_t B, const float* h,
+                          const float* dy, void* workspace, float* dw1t, float* dw2t,
+                          hipStream_t stream);
+
 /* ---------------------------------------------------------- gradients */
 
 /*

@@ -110,6 +110,13 @@ SIGNATURES = {
                                     ctypes.c_char_p, _STREAM]),
     "tn_cppn_query": (ctypes.c_int, [_POP, _TR, ctypes.POINTER(TnSubstrate), ctypes.c_void_p,
                                      ctypes.c_void_p, c_float_p, c_float_p, _STREAM]),
+    "tn_substrate_workspace_size": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,
+                                                   ctypes.c_int32, ctypes.c_int64,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_substrate_backward": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_int32, c_float_p, c_float_p,
+                                             ctypes.c_void_p, c_float_p, c_float_p, _STREAM]),
     "tn_substrate_forward": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_int32, c_float_p, c_float_p,

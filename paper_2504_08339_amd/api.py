@@ -357,3 +357,28 @@ def substrate_forward(w1t: torch.Tensor, w2t: torch.Tensor, x: torch.Tensor, gri
         ctypes.c_void_p(x.data_ptr()), stride, B, _p(h, _abi.c_float_p), _p(y, _abi.c_float_p),
         _stream(x.device)))
     return h, y
+
+
+def substrate_backward(w2t: torch.Tensor, x: torch.Tensor, h: torch.Tensor, dy: torch.Tensor,
+                       grid: int = 32, n_out: int = 8, threshold: float = 0.2):
+    """(dw1t [P][S][S], dw2t [P][n_out][S]) float32: gradient of sum(dy * y)
+    with respect to the substrate weights the forward used."""
+    sub = _substrate(grid, n_out, threshold)
+    S = int(grid) * int(grid)
+    P = w2t.shape[0]
+    B, stride = (x.shape[0], 0) if x.dim() == 2 else (x.shape[1], x.shape[1] * x.shape[2])
+    for t, dt in ((w2t, torch.bfloat16), (x, torch.bfloat16), (h, torch.float32),
+                  (dy, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise TypeError("w2t, x: contiguous bfloat16; h, dy: contiguous float32")
+    n = ctypes.c_size_t()
+    _check("tn_substrate_workspace_size", _lib.tn_substrate_workspace_size(
+        ctypes.byref(sub), P, B, stride, ctypes.byref(n)))
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=x.device)
+    dw1t = torch.empty((P, S, S), dtype=torch.float32, device=x.device)
+    dw2t = torch.empty((P, n_out, S), dtype=torch.float32, device=x.device)
+    _check("tn_substrate_backward", _lib.tn_substrate_backward(
+        ctypes.byref(sub), P, ctypes.c_void_p(w2t.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+        stride, B, _p(h, _abi.c_float_p), _p(dy, _abi.c_float_p), ctypes.c_void_p(ws.data_ptr()),
+        _p(dw1t, _abi.c_float_p), _p(dw2t, _abi.c_float_p), _stream(x.device)))
+    return dw1t, dw2t

@@ -23,6 +23,11 @@ int launch_cppn_query(const tn_population& p, const tn_transformed& t, const tn_
 int launch_substrate_forward(const tn_substrate& sub, int P, const uint16_t* w1t,
                              const uint16_t* w2t, const uint16_t* x, int64_t x_stride, int B,
                              float* h, float* y, hipStream_t stream);
+size_t substrate_workspace_bytes(const tn_substrate& sub, int P, int B, int64_t x_stride);
+int launch_substrate_backward(const tn_substrate& sub, int P, const uint16_t* w2t,
+                              const uint16_t* x, int64_t x_stride, int B, const float* h,
+                              const float* dy, void* workspace, float* dw1t, float* dw2t,
+                              hipStream_t stream);
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
@@ -315,6 +320,32 @@ int tn_substrate_forward(const tn_substrate* sub, int32_t P, const uint16_t* w1t
   if (P == 0 || B == 0) return TN_OK;
   if (!w1t || !w2t || !x || !h || !y) return TN_EINVAL;
   return launch_substrate_forward(*sub, P, w1t, w2t, x, x_genome_stride, B, h, y, stream);
+}
+
+int tn_substrate_workspace_size(const tn_substrate* sub, int32_t P, int32_t B,
+                                int64_t x_genome_stride, size_t* bytes) {
+  if (!bytes) return TN_EINVAL;
+  int rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  if (P < 0 || B < 0 || x_genome_stride < 0) return TN_EINVAL;
+  *bytes = substrate_workspace_bytes(*sub, P, B, x_genome_stride);
+  return TN_OK;
+}
+
+int tn_substrate_backward(const tn_substrate* sub, int32_t P, const uint16_t* w2t,
+                          const uint16_t* x, int64_t x_genome_stride, int32_t B, const float* h,
+                          const float* dy, void* workspace, float* dw1t, float* dw2t,
+                          hipStream_t stream) {
+  int rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  if (P < 0 || B < 0 || x_genome_stride < 0) return TN_EINVAL;
+  if (sub->n_out > 32 || (int64_t)B * sub->n_out > 16384) return TN_EUNSUPPORTED;
+  const int64_t S = (int64_t)sub->grid * sub->grid;
+  if (x_genome_stride > 0 && x_genome_stride < (int64_t)B * S) return TN_ESHAPE;
+  if (P == 0) return TN_OK;
+  if (!w2t || !x || !h || !dy || !workspace || !dw1t || !dw2t) return TN_EINVAL;
+  return launch_substrate_backward(*sub, P, w2t, x, x_genome_stride, B, h, dy, workspace, dw1t,
+                                   dw2t, stream);
 }
 
 }  // extern "C"

@@ -131,26 +131,38 @@ __global__ __launch_bounds__(256) void cppn_query_kernel(
 
 // ----------------------------------------------------------------- hidden
 
-// One wavefront per 64 x 64 tile of H (rows b, columns t) of one genome:
-// Z[b][t] = sum_s X[b][s] w1t[t][s] over K steps of 32 with 16 MFMA
-// 16x16x32 per step, then H = tanh(Z) in fp32. Operand fragments are loaded
-// straight from global memory (16 bytes per lane: 8 consecutive s of one row),
-// the same k-ordering on both operands. Rows b >= B read zeros and are not
-// stored.
-__global__ __launch_bounds__(256) void substrate_hidden_kernel(
-    const uint16_t* __restrict__ x, int64_t x_stride, const uint16_t* __restrict__ w1t, int S,
-    int B, int m_tiles, int n_tiles, int64_t n_items, float* __restrict__ h) {
+// Batched C[g][m][n] = sum_k A[g][m][k] * B[g][n][k] (bfloat16 operands, both
+// contiguous along k; float32 accumulation), one wavefront per 64 x 64 tile of
+// C: K steps of 32 with 16 MFMA 16x16x32 per step. Operand fragments are
+// loaded straight from global memory (16 bytes per lane: 8 consecutive k of
+// one row), with the same k-ordering on both operands. Rows m >= M or n >= N
+// read zeros and are not stored; K is a multiple of 32. kTanh applies tanh in
+// the epilogue (the substrate's hidden layer).
+struct GemmArgs {
+  const uint16_t* a;
+  int64_t lda, a_batch;
+  const uint16_t* b;
+  int64_t ldb, b_batch;
+  float* c;
+  int64_t ldc, c_batch;
+  int M, N, K;
+  int m_tiles, n_tiles;
+  int64_t n_items;
+};
+
+template <bool kTanh>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs p) {
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-  if (item >= n_items) return;  // wavefront-uniform; the kernel has no barrier
-  const int per_g = m_tiles * n_tiles;
+  if (item >= p.n_items) return;  // wavefront-uniform; the kernel has no barrier
+  const int per_g = p.m_tiles * p.n_tiles;
   const int g = (int)(item / per_g);
   const int r = (int)(item - (int64_t)g * per_g);
-  const int mt = r / n_tiles, nt = r - mt * n_tiles;
+  const int mt = r / p.n_tiles, nt = r - mt * p.n_tiles;
   const int m0 = mt * 64, n0 = nt * 64;
-  const uint16_t* X = x + (int64_t)g * x_stride;
-  const uint16_t* Wt = w1t + (int64_t)g * S * S;
+  const uint16_t* A = p.a + (int64_t)g * p.a_batch;
+  const uint16_t* Bm = p.b + (int64_t)g * p.b_batch;
   const int li = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc[4][4];
 #pragma unroll
@@ -158,13 +170,13 @@ __global__ __launch_bounds__(256) void substrate_hidden_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
   const bf16x8 zero8 = {};
-  for (int k0 = 0; k0 < S; k0 += 32) {
+  for (int k0 = 0; k0 < p.K; k0 += 32) {
     bf16x8 a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = m0 + 16 * i + li;
-      a[i] = row < B ? *reinterpret_cast<const bf16x8*>(X + (int64_t)row * S + k0 + kq) : zero8;
-      b[i] = *reinterpret_cast<const bf16x8*>(Wt + (int64_t)(n0 + 16 * i + li) * S + k0 + kq);
+      const int ra = m0 + 16 * i + li, rb = n0 + 16 * i + li;
+      a[i] = ra < p.M ? *reinterpret_cast<const bf16x8*>(A + ra * p.lda + k0 + kq) : zero8;
+      b[i] = rb < p.N ? *reinterpret_cast<const bf16x8*>(Bm + rb * p.ldb + k0 + kq) : zero8;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -172,7 +184,7 @@ __global__ __launch_bounds__(256) void substrate_hidden_kernel(
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
-  float* Hg = h + (int64_t)g * B * S;
+  float* C = p.c + (int64_t)g * p.c_batch;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -182,8 +194,21 @@ __global__ __launch_bounds__(256) void substrate_hidden_kernel(
         // D[16x16] fragment: lane holds rows 4*(lane/16) + e, column lane % 16
         const int row = m0 + 16 * i + (lane >> 4) * 4 + e;
         const int col = n0 + 16 * j + li;
-        if (row < B) Hg[(int64_t)row * S + col] = act_tanh(acc[i][j][e]);
+        if (row < p.M && col < p.N)
+          C[row * p.ldc + col] = kTanh ? act_tanh(acc[i][j][e]) : acc[i][j][e];
       }
+}
+
+template <bool kTanh>
+int launch_gemm(GemmArgs p, int batch, hipStream_t stream) {
+  p.m_tiles = (p.M + 63) / 64;
+  p.n_tiles = (p.N + 63) / 64;
+  p.n_items = (int64_t)batch * p.m_tiles * p.n_tiles;
+  if (p.n_items == 0) return TN_OK;
+  const int64_t grid = (p.n_items + 3) / 4;
+  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
+  hipLaunchKernelGGL((gemm_nt_kernel<kTanh>), dim3((unsigned)grid), dim3(256), 0, stream, p);
+  return check_launch();
 }
 
 // ----------------------------------------------------------------- output
@@ -208,6 +233,86 @@ __global__ __launch_bounds__(256) void substrate_output_kernel(
     float acc = 0.0f;
     for (int t = 0; t < S; ++t) acc = fmaf(bf16_float(bf16_bits(hr[t])), bf16_float(wr[t]), acc);
     y[((int64_t)g * B + b) * m + j] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- backward
+
+constexpr int kMaxOutBwd = 32;
+
+// For L = sum(dY * Y), per hidden unit t of genome g (one thread each):
+//   dw2t[j][t] = sum_b H[b][t] dY[b][j]                  (ascending b)
+//   dz[b][t]   = (sum_j dY[b][j] w2t[j][t]) (1 - H[b][t]^2)
+// dz is stored transposed and rounded to bfloat16, dzt[t][b], rows padded
+// with zeros to Kp (a multiple of 32) for the weight-gradient GEMM.
+__global__ __launch_bounds__(256) void substrate_grad_out_kernel(
+    const float* __restrict__ h, const uint16_t* __restrict__ w2t, const float* __restrict__ dy,
+    int S, int B, int Kp, int m, int wg_per_g, uint16_t* __restrict__ dzt,
+    float* __restrict__ dw2t) {
+  extern __shared__ __align__(16) float dys[];
+  const int g = blockIdx.x / wg_per_g;
+  const int t = (blockIdx.x - g * wg_per_g) * blockDim.x + threadIdx.x;
+  const float* D = dy + (int64_t)g * B * m;
+  for (int i = threadIdx.x; i < B * m; i += blockDim.x) dys[i] = D[i];
+  __syncthreads();
+  if (t >= S) return;
+  float w2[kMaxOutBwd], acc[kMaxOutBwd];
+#pragma unroll
+  for (int j = 0; j < kMaxOutBwd; ++j) {
+    w2[j] = j < m ? bf16_float(w2t[((int64_t)g * m + j) * S + t]) : 0.0f;
+    acc[j] = 0.0f;
+  }
+  const float* H = h + (int64_t)g * B * S + t;
+  uint16_t* Z = dzt + ((int64_t)g * S + t) * Kp;
+  for (int b0 = 0; b0 < Kp; b0 += 8) {
+    uint16_t pack[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + u;
+      float dz = 0.0f;
+      if (b < B) {
+        const float hb = H[(int64_t)b * S];
+        const float* d = dys + b * m;
+        float up = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kMaxOutBwd; ++j)
+          if (j < m) {
+            up = fmaf(d[j], w2[j], up);
+            acc[j] = fmaf(hb, d[j], acc[j]);
+          }
+        dz = up * fmaf(-hb, hb, 1.0f);
+      }
+      pack[u] = bf16_bits(dz);
+    }
+    uint4 v;
+    v.x = pack[0] | ((uint32_t)pack[1] << 16);
+    v.y = pack[2] | ((uint32_t)pack[3] << 16);
+    v.z = pack[4] | ((uint32_t)pack[5] << 16);
+    v.w = pack[6] | ((uint32_t)pack[7] << 16);
+    *reinterpret_cast<uint4*>(Z + b0) = v;
+  }
+  for (int j = 0; j < m; ++j) dw2t[((int64_t)g * m + j) * S + t] = acc[j];
+}
+
+// xt[g][s][b] = x[g][b][s] (bfloat16 bits), rows padded with zeros to Kp.
+__global__ __launch_bounds__(256) void transpose_x_kernel(const uint16_t* __restrict__ x,
+                                                          int64_t x_stride, int S, int B, int Kp,
+                                                          int wg_per_g, uint16_t* __restrict__ xt) {
+  const int g = blockIdx.x / wg_per_g;
+  const int s = (blockIdx.x - g * wg_per_g) * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint16_t* X = x + (int64_t)g * x_stride + s;
+  uint16_t* T = xt + ((int64_t)g * S + s) * Kp;
+  for (int b0 = 0; b0 < Kp; b0 += 8) {
+    uint16_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = b0 + u < B ? X[(int64_t)(b0 + u) * S] : (uint16_t)0;
+    uint4 q;
+    q.x = v[0] | ((uint32_t)v[1] << 16);
+    q.y = v[2] | ((uint32_t)v[3] << 16);
+    q.z = v[4] | ((uint32_t)v[5] << 16);
+    q.w = v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4*>(T + b0) = q;
   }
 }
 
@@ -251,14 +356,20 @@ int launch_substrate_forward(const tn_substrate& sub, int P, const uint16_t* w1t
                              const uint16_t* w2t, const uint16_t* x, int64_t x_stride, int B,
                              float* h, float* y, hipStream_t stream) {
   const int S = sub.grid * sub.grid;
-  const int m_tiles = (B + 63) / 64, n_tiles = S / 64;
-  const int64_t waves = (int64_t)P * m_tiles * n_tiles;
-  if (waves == 0) return TN_OK;
-  const int64_t grid = (waves + 3) / 4;
-  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
-  hipLaunchKernelGGL(substrate_hidden_kernel, dim3((unsigned)grid), dim3(256), 0, stream, x,
-                     x_stride, w1t, S, B, m_tiles, n_tiles, waves, h);
-  int rc = check_launch();
+  GemmArgs ga{};
+  ga.a = x;
+  ga.lda = S;
+  ga.a_batch = x_stride;
+  ga.b = w1t;
+  ga.ldb = S;
+  ga.b_batch = (int64_t)S * S;
+  ga.c = h;
+  ga.ldc = S;
+  ga.c_batch = (int64_t)B * S;
+  ga.M = B;
+  ga.N = S;
+  ga.K = S;
+  int rc = launch_gemm<true>(ga, P, stream);
   if (rc != TN_OK) return rc;
   const int rows_per_wg = std::max(1, 256 / sub.n_out);
   const int wg_per_g = (B + rows_per_wg - 1) / rows_per_wg;
@@ -268,6 +379,51 @@ int launch_substrate_forward(const tn_substrate& sub, int P, const uint16_t* w1t
   hipLaunchKernelGGL(substrate_output_kernel, dim3((unsigned)(P * wg_per_g)), dim3(256), lds,
                      stream, h, w2t, S, B, sub.n_out, rows_per_wg, wg_per_g, y);
   return check_launch();
+}
+
+size_t substrate_workspace_bytes(const tn_substrate& sub, int P, int B, int64_t x_stride) {
+  const int64_t S = (int64_t)sub.grid * sub.grid;
+  const int64_t Kp = ((int64_t)B + 31) / 32 * 32;
+  const int64_t px = x_stride == 0 ? 1 : P;
+  return (size_t)(2 * S * Kp * (P + px));
+}
+
+int launch_substrate_backward(const tn_substrate& sub, int P, const uint16_t* w2t,
+                              const uint16_t* x, int64_t x_stride, int B, const float* h,
+                              const float* dy, void* workspace, float* dw1t, float* dw2t,
+                              hipStream_t stream) {
+  const int S = sub.grid * sub.grid, m = sub.n_out;
+  const int Kp = (B + 31) / 32 * 32;
+  const int px = x_stride == 0 ? 1 : P;
+  uint16_t* dzt = static_cast<uint16_t*>(workspace);
+  uint16_t* xt = dzt + (int64_t)P * S * Kp;
+  const int wg_per_g = (S + 255) / 256;
+  const size_t lds = sizeof(float) * (size_t)B * m;
+  int rc = allow_lds((const void*)substrate_grad_out_kernel, lds);
+  if (rc != TN_OK) return rc;
+  hipLaunchKernelGGL(substrate_grad_out_kernel, dim3((unsigned)(P * wg_per_g)), dim3(256), lds,
+                     stream, h, w2t, dy, S, B, Kp, m, wg_per_g, dzt, dw2t);
+  rc = check_launch();
+  if (rc != TN_OK) return rc;
+  hipLaunchKernelGGL(transpose_x_kernel, dim3((unsigned)(px * wg_per_g)), dim3(256), 0, stream, x,
+                     x_stride, S, B, Kp, wg_per_g, xt);
+  rc = check_launch();
+  if (rc != TN_OK) return rc;
+  // dw1t[t][s] = sum_b dz[b][t] x[b][s]
+  GemmArgs ga{};
+  ga.a = dzt;
+  ga.lda = Kp;
+  ga.a_batch = (int64_t)S * Kp;
+  ga.b = xt;
+  ga.ldb = Kp;
+  ga.b_batch = x_stride == 0 ? 0 : (int64_t)S * Kp;
+  ga.c = dw1t;
+  ga.ldc = S;
+  ga.c_batch = (int64_t)S * S;
+  ga.M = S;
+  ga.N = S;
+  ga.K = Kp;
+  return launch_gemm<false>(ga, P, stream);
 }
 
 }  // namespace tn

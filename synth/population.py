@@ -488,6 +488,13 @@ def subset(pop: Population, genomes: Sequence[int]) -> Population:
                           *[getattr(pop, n)[genomes].copy() for n in
                             ("node_key", "node_bias", "node_resp", "node_act", "node_agg",
                              "conn_in", "conn_out", "conn_w", "conn_en")])
+    if not genomes:
+        z = lambda a: a[:0].copy()
+        return Population(pop.n_in, pop.n_out, pop.N_max, pop.C_max,
+                          *[z(getattr(pop, n)) for n in
+                            ("node_key", "node_bias", "node_resp", "node_act", "node_agg",
+                             "conn_in", "conn_out", "conn_w", "conn_en")],
+                          np.zeros(1, np.int64), np.zeros(1, np.int64))
     nb = [pop.node_rows(g) for g in genomes]
     cb = [pop.conn_rows(g) for g in genomes]
     node_off = np.zeros(len(genomes) + 1, np.int64)

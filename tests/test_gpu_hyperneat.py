@@ -192,3 +192,30 @@ def test_full_size_sampled():
         ok = (np.abs(np.abs(ref_w) - THR) > 1e-4)
         expect = _bf16_value(_bf16_bits(hn.threshold(ref_w).astype(np.float32)))
         assert np.all((np.abs(got - expect) <= 2.0 ** -7 * np.abs(expect)) | ~ok)   # one bf16 step
+
+
+@pytest.mark.parametrize("shared", [True, False])
+def test_substrate_backward_matches_oracle(shared):
+    """Gradients of sum(dY * Y) against the oracle's substrate adjoint computed
+    from the GPU's own h, weights and inputs. dw2t: float32 sums of B <= 128
+    terms, |err| <= 2^-17 * sum_b |h dy|; dw1t: dZ rounded to bfloat16 (2^-9)
+    plus float32 accumulation, |err| <= 2^-8 * sum_b |dz_b x_b|."""
+    import paper_2504_08339_amd as tn
+    P, B = 3, 100
+    _, pop, w1t, w2t, xb, h, y = _substrate_case(P, B, shared)
+    dy = np.random.default_rng(12).standard_normal((P, B, NOUT)).astype(np.float32)
+    dw1t, dw2t = tn.substrate_backward(w2t, xb, torch.from_numpy(h).cuda(),
+                                       torch.from_numpy(dy).cuda(), GRID, NOUT, THR)
+    dw1t, dw2t = host(dw1t), host(dw2t)
+    W2 = _bf16_value(_bits16(w2t))          # [P][j][t]
+    Xv = _bf16_value(_bits16(xb))
+    for g in range(P):
+        Xg = Xv if shared else Xv[g]
+        H = h[g].astype(np.float64)
+        dY = dy[g].astype(np.float64)
+        dW1, dW2 = hn.substrate_backward(Xg, W2[g].T, H, dY)      # [s][t], [t][j]
+        b2 = 2.0 ** -17 * (np.abs(H).T @ np.abs(dY)) + 1e-30
+        assert np.all(np.abs(dw2t[g].T - dW2) <= b2), g
+        dZ = (dY @ W2[g]) * (1.0 - H * H)
+        b1 = 2.0 ** -8 * (np.abs(Xg).T @ np.abs(dZ)) + 1e-30            # [s][t]
+        assert np.all(np.abs(dw1t[g].T - dW1) <= b1), g
