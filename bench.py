@@ -2,16 +2,31 @@
 """Throughput of the population-evaluation hot path on one MI355X.
 
 Prints ONE JSON line. A step is one pass of the hot path over one batch of
-synthetic input, with every input already resident in device memory:
+synthetic input, with every input already resident in device memory.
 
-  control  (default) 1000 genomes, 17 -> 6, N_max 64, C_max 256, 1000 N(0,1)
-           observations per genome: transform + forward (1e6 genome-forward
-           passes) + the 1000 x 1000 compatibility distance matrix.
+Headline workload (`value`): uneven-size batching, 10,000 genomes with
+log-uniform 10..500 hidden nodes and 2..4x as many connections (at most 2000),
+27 inputs -> 8 outputs, ragged layout, 256 N(0,1) observations per genome:
+one step = the batched forward of the whole population by a tuned plan, its
+length buckets run as persistent kernels captured in one hipGraph
+(2.56e6 genome-forward passes). The same plan's plain form (one ordinary
+launch per bucket) is timed over the same number of steps for the comparison.
 
-`value` is genome-forward passes per second over the timed steps (P * B per
-step / time per step). Each library call is bracketed by HIP events on the
-stream it runs on; the dominant call's average duration gives the roofline
-figure. The CPU oracle is timed on a bounded sample for `cpu_baseline`.
+Beside it (`workloads`), each with its own timed steps and roofline:
+  control          1000 genomes 17 -> 6 (N_max 64, C_max 256), 1000 obs each:
+                   transform + forward + 1000 x 1000 compatibility distance;
+  differentiation  4096 genomes 4 -> 2, 1024 shared samples: forward + adjoint
+                   with the fused MSE loss;
+  hyperneat        1000 CPPNs on a 32x32 / 32x32 / 8 grid substrate, 128 obs per
+                   genome: CPPN query + substrate forward + substrate backward.
+
+`value` is genome-forward passes per second (P * B per step / time per step).
+The roofline object is for the dominant kernel of the headline step: every
+bucket's persistent kernel is also launched alone, bracketed by HIP events on
+the stream it runs on, and the slowest one's algorithmic bytes (observations
+read, outputs written and the program words its genomes read, counted from
+the actual population) over its average duration give `achieved`. The CPU
+oracle is timed on a bounded sample for `cpu_baseline`.
 """
 from __future__ import annotations
 
@@ -27,6 +42,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("genome-forward-passes/s (pop×obs) + % HBM roofline; "
           "batched-persistent vs plain launch")
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def _args():
@@ -34,18 +50,23 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="control", choices=["control"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="rough budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the other workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
-class CallTimer:
-    """HIP events around each library call, on torch's current stream (the stream
-    every call is launched on)."""
+def _log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events around calls on torch's current stream (the stream every
+    library call is launched on)."""
 
     def __init__(self, torch):
         self.torch = torch
@@ -60,21 +81,174 @@ class CallTimer:
         self.pairs.setdefault(name, []).append((ev0, ev1))
         return r
 
-    def reset(self):
-        self.pairs = {}
-
     def mean_ms(self):
         return {n: sum(a.elapsed_time(b) for a, b in v) / len(v) for n, v in self.pairs.items()}
 
 
-def control_workload(torch, tn, synth):
+def timed_steps(torch, step, steps, warmup):
+    """Warm-up steps, then exactly `steps` timed steps between synchronisations;
+    returns (ms per step by the host clock, per-call mean ms by HIP events)."""
+    t = Timer(torch)
+    for _ in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    t = Timer(torch)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(t)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps, t.mean_ms()
+
+
+def device_population(torch, tn, pop):
+    arrays = {k: getattr(pop, k) for k in ("node_key", "node_bias", "node_resp", "node_act",
+                                           "node_agg", "conn_in", "conn_out", "conn_w", "conn_en")}
+    kw = {}
+    if pop.ragged:
+        kw = {"node_off": pop.node_off, "conn_off": pop.conn_off}
+    return tn.Population.from_numpy(pop.n_in, pop.n_out, pop.N_max, pop.C_max, arrays,
+                                    device="cuda", **kw)
+
+
+def genome_sizes(torch, pop, tr):
+    """(n_valid, enabled edges) per genome, read back from the transformation."""
+    import numpy as np
+    torch.cuda.synchronize()
+    nv = tr.n_valid.cpu().numpy()[:pop.P].astype(np.int64)
+    rp = tr.row_ptr.cpu().numpy()
+    if pop.ragged:
+        base = pop.node_off[:pop.P] + np.arange(pop.P)
+    else:
+        base = np.arange(pop.P) * (pop.N_max + 1)
+    return nv, rp[base + nv].astype(np.int64)
+
+
+# ------------------------------------------------------------------ batching
+
+def batching(torch, tn, synth, args):
+    import numpy as np
+    pop = synth.batching_population()
+    B = 256
+    obs_np = synth.normal_obs(pop.P, B, pop.n_in, synth.CONFIG_SEEDS["batching"] + 100)
+    dp = device_population(torch, tn, pop)
+    obs = torch.from_numpy(obs_np).cuda()
+    tr = tn.transform(dp)
+    out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device="cuda")
+    _log("batching: plan + tuning")
+    plan = tn.Plan(dp, tr, B)
+    plan.tune(obs, out)
+    buckets = plan.buckets()
+    nv, ne = genome_sizes(torch, pop, tr)
+    I, O = pop.n_in, pop.n_out
+
+    # algorithmic bytes per genome: observations in, outputs out, and the
+    # program words the engine reads (register engine: 16 B per position and
+    # 8 B per edge; LDS engine: row_ptr, level, fn, bias, resp, row 24 B per
+    # position + 8 B per edge), plus the io positions
+    prog_rows = tr.prog_rows.cpu().numpy()[:pop.P]
+    reg = prog_rows <= 64
+    per_genome = (4 * B * (I + O) + np.where(reg, 16 * nv, 24 * nv + 4) + 8 * ne
+                  + 4 * (I + O) + 12)
+    total_bytes = int(per_genome.sum())
+    lists = bucket_members(pop, tr, buckets)
+    bucket_bytes = [int(per_genome[m].sum()) for m in lists]
+
+    _log("batching: persistent graph steps")
+    graph_ms, _ = timed_steps(torch, lambda t: t("graph", plan.forward, obs, out),
+                              args.steps, args.warmup)
+    _log("batching: plain per-bucket steps")
+    plain_ms, _ = timed_steps(torch, lambda t: t("plain", plan.forward_buckets, obs, out),
+                              args.steps, args.warmup)
+    _log("batching: buckets one by one")
+
+    def per_bucket(t):
+        for i in range(len(buckets)):
+            t(f"bucket{i}", plan.forward_bucket, i, obs, out, True)
+    _, bms = timed_steps(torch, per_bucket, args.steps, args.warmup)
+    bucket_ms = [bms[f"bucket{i}"] for i in range(len(buckets))]
+    dom = int(np.argmax(bucket_ms))
+    achieved = bucket_bytes[dom] / (bucket_ms[dom] * 1e-3) / 1e9
+    eng = {1: "lds", 2: "register"}
+    kern = ("forward_reg_queue_kernel" if buckets[dom]["engine"] == 2
+            else "forward_queue_kernel")
+    roofline = {"bound": "hbm", "kernel": f"{kern} (bucket {dom}: "
+                f"{eng[buckets[dom]['engine']]} engine, rows <= {buckets[dom]['rows_class']})",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes": bucket_bytes[dom], "avg_ms": bucket_ms[dom]}
+    passes = pop.P * B
+    info = {
+        "workload": "batching: 10000 genomes, hidden nodes log-uniform 10..500, "
+                    "connections 2-4x hidden (max 2000), 27 -> 8, ragged layout, 256 N(0,1) "
+                    "observations per genome; step = batched forward by a tuned plan "
+                    "(persistent bucket kernels in one hipGraph)",
+        "population": pop.P, "obs_per_genome": B, "n_in": I, "n_out": O,
+        "mean_nodes": float(nv.mean()), "mean_enabled_edges": float(ne.mean()),
+    }
+    res = {
+        "passes": passes, "ms_per_step": graph_ms, "roofline": roofline, "config": info,
+        "whole_step_hbm_frac": total_bytes / (graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_step": total_bytes,
+        "plain_per_bucket": {"value": passes / (plain_ms * 1e-3), "ms_per_step": plain_ms,
+                             "persistent_graph_speedup": plain_ms / graph_ms},
+        "buckets": [{**b, "ms_alone": m, "algorithmic_bytes": by}
+                    for b, m, by in zip(buckets, bucket_ms, bucket_bytes)],
+    }
+    return res, pop, obs_np
+
+
+def bucket_members(pop, tr, buckets):
+    """Genome indices of each bucket, by the plan's documented rule."""
+    import numpy as np
+    st = tr.status.cpu().numpy()[:pop.P]
+    pr = tr.prog_rows.cpu().numpy()[:pop.P]
+    nr = tr.n_rows.cpu().numpy()[:pop.P]
+    lists, lo = [], None
+    for b in buckets:
+        if b["engine"] == 2 and b["rows_class"] == 32:
+            m = (st != 0) | (pr <= 32)
+        elif b["engine"] == 2:
+            m = (st == 0) & (pr > 32) & (pr <= 64)
+        else:
+            m = (st == 0) & (pr > 64) & (nr <= b["rows_class"])
+            if lo is not None:
+                m &= nr > lo
+            lo = b["rows_class"]
+        lists.append(np.flatnonzero(m))
+    return lists
+
+
+def cpu_baseline_forward(pop, obs, budget_s, label):
+    """The oracle as it stands, one process: transform + forward of a sample of
+    genomes with all their observations, scaled to passes per second."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(0)
+    order = rng.permutation(pop.P)
+    t0 = time.perf_counter()
+    n_g = 0
+    while time.perf_counter() - t0 < budget_s and n_g < pop.P:
+        g = int(order[n_g])
+        gen = oracle.decode(pop, g)
+        oracle.forward(gen, oracle.transform(gen), obs[g])
+        n_g += 1
+    sec = time.perf_counter() - t0
+    B = obs.shape[1]
+    return {"value": n_g * B / sec, "unit": "genome-forward-passes/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_g} random genomes of the {label} population x all {B} observations "
+                      f"each (decode + transform + forward), float64 NumPy, one process, "
+                      f"{sec:.1f} s"}
+
+
+# ------------------------------------------------------------------- control
+
+def control(torch, tn, synth, args):
     import numpy as np
     pop = synth.control_population()
     B = 1000
     obs_np = synth.normal_obs(pop.P, B, pop.n_in, synth.CONFIG_SEEDS["control"] + 100)
-    arrays = {k: getattr(pop, k) for k in ("node_key", "node_bias", "node_resp", "node_act",
-                                           "node_agg", "conn_in", "conn_out", "conn_w", "conn_en")}
-    dp = tn.Population.from_numpy(pop.n_in, pop.n_out, pop.N_max, pop.C_max, arrays, device="cuda")
+    dp = device_population(torch, tn, pop)
     obs = torch.from_numpy(obs_np).cuda()
     tr = tn.Transformed(dp)
     out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device="cuda")
@@ -82,70 +256,99 @@ def control_workload(torch, tn, synth):
     dist = (torch.empty((pop.P, pop.P), dtype=torch.float32, device="cuda"),
             torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"),
             torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"))
-
-    def step(timer):
-        timer("transform", tn.transform, dp, out=tr)
-        timer("forward", tn.forward, dp, tr, obs, out=out)
-        timer("distance", tn.distance, dp, workspace=ws, out=dist)
-
-    # algorithmic bytes, counted from the actual population
     tn.transform(dp, out=tr)
-    torch.cuda.synchronize()
-    nv = tr.n_valid.cpu().numpy().astype(np.int64)
-    rp = tr.row_ptr.cpu().numpy().reshape(pop.P, pop.N_max + 1)
-    ne = rp[np.arange(pop.P), nv].astype(np.int64)
+    rows = int(tr.n_rows.max().item())
+    tile = dict(engine=tn.TN_ENGINE_LDS, obs_per_lane=4, waves_per_genome=4, rows=rows)
+
+    def step(t):
+        t("transform", tn.transform, dp, out=tr)
+        t("forward", tn.forward, dp, tr, obs, out=out, **tile)
+        t("distance", tn.distance, dp, workspace=ws, out=dist)
+    step_ms, ms = timed_steps(torch, step, args.steps, args.warmup)
+    nv, ne = genome_sizes(torch, pop, tr)
     I, O = pop.n_in, pop.n_out
-    fwd_bytes = (4 * pop.P * B * I + 4 * pop.P * B * O          # observations in, outputs out
-                 + int(np.sum(4 * (nv + 1) + 12 * nv + 8 * ne))  # row_ptr, fn/bias/resp, edges
-                 + 4 * pop.P * (I + O) + 8 * pop.P)              # io positions, status/n_valid
-    valid_rows = pop.nbytes_valid()
-    tr_bytes = valid_rows + int(np.sum(20 * nv + 4 * (nv + 1) + 12 * ne)) + 4 * pop.P * (I + O + 2)
-    info = {
-        "workload": "control-policy: 1000 genomes, 17 inputs -> 6 outputs, N_max 64, C_max 256, "
-                    "1000 N(0,1) observations per genome; step = transform + forward + "
-                    "1000x1000 compatibility distance",
-        "population": pop.P, "obs_per_genome": B, "n_in": I, "n_out": O, "N_max": pop.N_max,
-        "C_max": pop.C_max, "mean_nodes": float(nv.mean()), "mean_enabled_edges": float(ne.mean()),
+    fwd_bytes = (4 * pop.P * B * (I + O) + int(np.sum(4 * (nv + 1) + 20 * nv + 8 * ne))
+                 + 4 * pop.P * (I + O) + 8 * pop.P)
+    achieved = fwd_bytes / (ms["forward"] * 1e-3) / 1e9
+    return {
+        "workload": "control-policy: 1000 genomes, 17 -> 6, N_max 64, C_max 256, 1000 N(0,1) "
+                    "observations per genome; step = transform + forward (LDS engine, 4 obs "
+                    f"per lane, 4 waves, {rows} rows) + 1000 x 1000 compatibility distance",
+        "value": pop.P * B / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
+        "ms_per_step": step_ms, "call_ms": ms,
+        "forward_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                             "algorithmic_bytes": fwd_bytes},
+        "distance_pairs_per_s": pop.P * pop.P / (ms["distance"] * 1e-3),
     }
-    bytes_per_call = {"forward": fwd_bytes, "transform": tr_bytes}
-    return pop, obs_np, step, pop.P * B, info, bytes_per_call
 
 
-def cpu_baseline_control(pop, obs, budget_s):
-    """The oracle as it stands, single process: transform + forward of a sample of
-    genomes (all their observations) and distances of a sample of pairs, each
-    scaled to the whole step."""
+# ----------------------------------------------------------- differentiation
+
+def differentiation(torch, tn, synth, args):
     import numpy as np
-    import oracle
-    rng = np.random.default_rng(0)
-    t0 = time.perf_counter()
-    n_g = 0
-    order = rng.permutation(pop.P)
-    while time.perf_counter() - t0 < 0.5 * budget_s and n_g < pop.P:
-        g = int(order[n_g])
-        gen = oracle.decode(pop, g)
-        oracle.forward(gen, oracle.transform(gen), obs[g])
-        n_g += 1
-    t_fwd = (time.perf_counter() - t0) / n_g
-    genes = {}
-    t1 = time.perf_counter()
-    n_p = 0
-    while time.perf_counter() - t1 < 0.5 * budget_s:
-        i, j = (int(x) for x in rng.integers(0, pop.P, 2))
-        for k in (i, j):
-            if k not in genes:
-                genes[k] = oracle.genome_genes(pop, k)
-        oracle.distance(genes[i], genes[j])
-        n_p += 1
-    t_pair = (time.perf_counter() - t1) / n_p
-    step_s = t_fwd * pop.P + t_pair * pop.P * pop.P
-    B = obs.shape[1]
-    return {"value": pop.P * B / step_s, "unit": "genome-forward-passes/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_g} genomes x {B} observations (transform + forward) and {n_p} "
-                      f"genome pairs (distance), float64 NumPy / Python, one process; "
-                      f"scaled to 1000 genomes + 1e6 pairs per step",
-            "seconds_per_step": step_s}
+    pop = synth.differentiation_population()
+    X = synth.uniform_inputs(1024, 4, synth.CONFIG_SEEDS["differentiation"] + 100)
+    T = synth.target_mlp(X, 32, 2, synth.CONFIG_SEEDS["differentiation"] + 200)
+    dp = device_population(torch, tn, pop)
+    tr = tn.transform(dp)
+    Xt, Tt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    step_ms, ms = timed_steps(
+        torch, lambda t: t("forward_backward_mse", tn.forward_backward_mse, dp, tr, Xt, Tt),
+        args.steps, args.warmup)
+    nv, ne = genome_sizes(torch, pop, tr)
+    # gradients written + program read twice (forward and reverse sweep) + data
+    by = int(4 * pop.P * (pop.C_max + pop.N_max) + 2 * np.sum(24 * nv + 8 * ne)
+             + X.nbytes + T.nbytes)
+    achieved = by / (ms["forward_backward_mse"] * 1e-3) / 1e9
+    return {
+        "workload": "differentiation: 4096 genomes 4 -> 2 (N_max 64, C_max 256), 1024 shared "
+                    "U(-1,1) samples, MSE against a fixed 4-32-2 tanh MLP; step = forward + "
+                    "adjoint (dL/dW, dL/db)",
+        "value": pop.P * 1024 / (step_ms * 1e-3), "unit": "sample-passes/s (forward+adjoint)",
+        "ms_per_step": step_ms, "roofline": {"bound": "hbm", "achieved": achieved,
+                                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                             "frac": achieved / HBM_PEAK_GBS,
+                                             "algorithmic_bytes": by},
+    }
+
+
+# ------------------------------------------------------------------ hyperneat
+
+def hyperneat(torch, tn, synth, args):
+    pop = synth.cppn_population()
+    dp = device_population(torch, tn, pop)
+    tr = tn.transform(dp)
+    grid, n_out, B = 32, 8, 128
+    S = grid * grid
+    g = torch.Generator().manual_seed(synth.CONFIG_SEEDS["cppn"] + 100)
+    xb = torch.randn((pop.P, B, S), generator=g).to(torch.bfloat16).cuda()
+    dy = torch.randn((pop.P, B, n_out), generator=g).cuda()
+    state = {}
+
+    def step(t):
+        w1t, w2t = t("cppn_query", tn.cppn_query, dp, tr, grid, n_out, 0.2)
+        h, y = t("substrate_forward", tn.substrate_forward, w1t, w2t, xb, grid, n_out)
+        t("substrate_backward", tn.substrate_backward, w2t, xb, h, dy, grid, n_out)
+        state["w"] = (w1t, w2t)
+    steps = max(2, args.steps // 4)
+    step_ms, ms = timed_steps(torch, step, steps, 1)
+    flops = 2.0 * pop.P * B * S * S + 2.0 * pop.P * B * S * n_out
+    w_bytes = 2 * pop.P * (S * S + S * n_out)
+    fwd_bytes = w_bytes + xb.numel() * 2 + 4 * pop.P * B * (S + n_out)
+    return {
+        "workload": "hyperneat: 1000 CPPNs 5 -> 1 (N_max 32, C_max 96) queried on a 32x32 / "
+                    "32x32 / 8 grid substrate (1,056,768 queries each), |w| < 0.2 -> 0, bf16; "
+                    "128 N(0,1) bf16 inputs per genome; step = query + substrate forward + "
+                    "substrate backward",
+        "ms_per_step": step_ms, "call_ms": ms, "steps": steps,
+        "queries_per_s": pop.P * (S * S + S * n_out) / (ms["cppn_query"] * 1e-3),
+        "substrate_forward": {
+            "tflops": flops / (ms["substrate_forward"] * 1e-3) / 1e12,
+            "mfma_frac": flops / (ms["substrate_forward"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+            "hbm_frac": fwd_bytes / (ms["substrate_forward"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes": fwd_bytes},
+    }
 
 
 def main():
@@ -160,46 +363,35 @@ def main():
     import paper_2504_08339_amd as tn
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    print("bench: building the control workload", file=sys.stderr, flush=True)
-    pop, obs_np, step, passes, info, bytes_per_call = control_workload(torch, tn, synth)
-    print("bench: timing", file=sys.stderr, flush=True)
-    timer = CallTimer(torch)
-    for _ in range(args.warmup):
-        step(timer)
-    torch.cuda.synchronize()
-    timer.reset()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(timer)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = timer.mean_ms()
-    step_ms = 1e3 * wall / args.steps
-
-    dominant = max(ms, key=ms.get)
-    roof_kernel = dominant if dominant in bytes_per_call else "forward"
-    achieved = bytes_per_call[roof_kernel] / (ms[roof_kernel] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": roof_kernel, "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "algorithmic_bytes": bytes_per_call[roof_kernel],
-                "avg_ms": ms[roof_kernel]}
+    _log("building the batching workload")
+    head, pop, obs_np = batching(torch, tn, synth, args)
+    others = {}
+    if not args.only_headline:
+        for name, fn in (("control", control), ("differentiation", differentiation),
+                         ("hyperneat", hyperneat)):
+            _log(f"workload {name}")
+            others[name] = fn(torch, tn, synth, args)
+            torch.cuda.empty_cache()
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-
     cpu = None
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline_control(pop, obs_np, args.cpu_seconds)
+        _log("timing the CPU oracle sample")
+        cpu = cpu_baseline_forward(pop, obs_np, args.cpu_seconds, "batching")
 
     line = {
-        "metric": METRIC, "value": passes / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic", "config": info, "kernel_ms": ms, "dominant_call": dominant,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "metric": METRIC, "value": head["passes"] / (head["ms_per_step"] * 1e-3),
+        "unit": "genome-forward-passes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": head["config"], "roofline": head["roofline"], "cpu_baseline": cpu,
+        "plain_per_bucket": head["plain_per_bucket"],
+        "whole_step_hbm_frac": head["whole_step_hbm_frac"],
+        "algorithmic_bytes_per_step": head["algorithmic_bytes_per_step"],
+        "buckets": head["buckets"], "workloads": others,
     }
     print(json.dumps(line))
 

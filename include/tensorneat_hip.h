@@ -357,6 +357,11 @@ int  tn_plan_forward_buckets(tn_plan* plan, const float* obs, int64_t obs_genome
                              float* out, hipStream_t stream);
 int  tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
                   const char* tune_cache, hipStream_t stream);
+/* Bucket i alone on `stream`: its persistent kernel (persistent != 0, after a
+ * zeroing kernel for its counter) or its plain launch; writes that bucket's
+ * genomes of out. For timing buckets one by one. */
+int  tn_plan_forward_bucket(tn_plan* plan, int32_t i, int32_t persistent, const float* obs,
+                            int64_t obs_genome_stride, float* out, hipStream_t stream);
 
 /* ---------------------------------------------------------- HyperNEAT */
 

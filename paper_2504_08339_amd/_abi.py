@@ -108,6 +108,8 @@ SIGNATURES = {
                                                c_float_p, _STREAM]),
     "tn_plan_tune": (ctypes.c_int, [ctypes.c_void_p, c_float_p, ctypes.c_int64, c_float_p,
                                     ctypes.c_char_p, _STREAM]),
+    "tn_plan_forward_bucket": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                              c_float_p, ctypes.c_int64, c_float_p, _STREAM]),
     "tn_cppn_query": (ctypes.c_int, [_POP, _TR, ctypes.POINTER(TnSubstrate), ctypes.c_void_p,
                                      ctypes.c_void_p, c_float_p, c_float_p, _STREAM]),
     "tn_substrate_workspace_size": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,

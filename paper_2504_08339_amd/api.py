@@ -263,7 +263,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:
             _lib.tn_plan_destroy(h)
             self._h = ctypes.c_void_p()
 
@@ -297,6 +297,14 @@ class Plan:
 
     def forward_buckets(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         return self._call("tn_plan_forward_buckets", obs, out)
+
+    def forward_bucket(self, i: int, obs: torch.Tensor, out: torch.Tensor,
+                       persistent: bool = True) -> torch.Tensor:
+        B, stride = _obs_stride(self.pop, obs)
+        _check("tn_plan_forward_bucket", _lib.tn_plan_forward_bucket(
+            self._h, i, 1 if persistent else 0, _p(obs, _abi.c_float_p), stride,
+            _p(out, _abi.c_float_p), _stream(self.pop.device)))
+        return out
 
     def tune(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None,
              tune_cache: Optional[str] = None) -> None:

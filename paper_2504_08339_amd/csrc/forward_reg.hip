@@ -27,14 +27,14 @@ struct RegArgs {
   int64_t target_stride;
   float scale, offset;
   int n_tiles;     // tiles of 64 observations per genome
-  int n_groups;    // workgroups per list entry (grid form without loss)
-  int per_wave;    // consecutive tiles per wavefront (grid form without loss)
+  int n_groups;    // tile chunks per list entry (grid form without loss)
+  int per_wave;    // tiles per chunk (grid form without loss)
   int rows;        // value rows in registers: 32 or 64
   int rows_lo;     // genomes with prog_rows <= rows_lo are left to another launch (-1: none)
   int skip_above;  // genomes needing more than `rows` rows are left to another launch
   const int32_t* genomes;  // genome list (nullptr: every genome, in order)
   int32_t* queue;          // persistent form: next item to take
-  int n_items;             // persistent form: list length * n_tiles
+  int n_items;             // grid form: list length * n_groups; persistent: * n_tiles
 };
 
 // Observations and outputs pass through LDS in chunks of up to kChunk
@@ -170,9 +170,11 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
   return sse;
 }
 
-// Grid form: workgroups over (list entry, group of tiles); with kLoss one
-// workgroup per list entry whose wavefronts share its tiles and reduce the
-// squared error in a fixed order.
+// Grid form: wavefront i of the launch takes item i = (list entry, chunk of
+// per_wave consecutive tiles), chunks of one entry being consecutive (so the
+// wavefronts of a workgroup mostly share a genome). With kLoss, one workgroup
+// per list entry whose wavefronts share its tiles and reduce the squared error
+// in a fixed order.
 template <int NB, bool kLoss>
 __global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
                                                                 float* __restrict__ loss) {
@@ -182,20 +184,21 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
   const int wave = threadIdx.x / kWave;
   const int W = blockDim.x / kWave;
   float* stg = stage_all + wave * kStage;
-  int item, t_begin, t_end, t_step;
+  int entry, t_begin, t_end, t_step;
   if (kLoss) {
-    item = blockIdx.x;
+    entry = blockIdx.x;
     t_begin = wave;
     t_end = a.n_tiles;
     t_step = W;
   } else {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    item = b / a.n_groups;
-    t_begin = ((b - item * a.n_groups) * W + wave) * a.per_wave;
+    const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * W + wave;
+    if (item >= a.n_items) return;  // wavefront-uniform; no barrier without kLoss
+    entry = (int)(item / a.n_groups);
+    t_begin = (int)(item - (int64_t)entry * a.n_groups) * a.per_wave;
     t_end = min(t_begin + a.per_wave, a.n_tiles);
     t_step = 1;
   }
-  const int g = a.genomes ? a.genomes[item] : item;
+  const int g = a.genomes ? a.genomes[entry] : entry;
   int st;
   const float sse = reg_genome<NB, kLoss>(TN_REG_ARGS, g, t_begin, t_end, t_step, stg, &st);
   if (kLoss && st != -2) {  // st is uniform over the workgroup
@@ -282,10 +285,10 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
   // enough wavefronts to fill the chip; each takes consecutive tiles of a genome
   const int want = std::max(1, std::min(n_tiles, (8192 + n_list - 1) / std::max(1, n_list)));
   a.per_wave = (n_tiles + want - 1) / want;
-  const int waves_needed = (n_tiles + a.per_wave - 1) / a.per_wave;
-  a.n_groups = (waves_needed + waves - 1) / waves;
-  const int64_t grid = (int64_t)n_list * a.n_groups;
-  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
+  a.n_groups = (n_tiles + a.per_wave - 1) / a.per_wave;  // chunks per list entry
+  a.n_items = (int)std::min<int64_t>((int64_t)n_list * a.n_groups, 0x7fffffff);
+  const int64_t grid = ((int64_t)n_list * a.n_groups + waves - 1) / waves;
+  if (grid > 0x7fffffff || (int64_t)n_list * a.n_groups > 0x7fffffff) return TN_EUNSUPPORTED;
   switch (tile.banks) {
     case 1: return launch_grid<1, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
     case 2: return launch_grid<2, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);

@@ -425,6 +425,22 @@ int tn_plan_forward(tn_plan* plan, const float* obs, int64_t obs_genome_stride, 
   return record_hip(hipGraphLaunch(plan->exec, stream));
 }
 
+int tn_plan_forward_bucket(tn_plan* plan, int32_t i, int32_t persistent, const float* obs,
+                           int64_t obs_genome_stride, float* out, hipStream_t stream) {
+  int rc = check_plan_call(plan, obs, obs_genome_stride, out);
+  if (rc != TN_OK) return rc;
+  if (i < 0 || i >= (int)plan->buckets.size()) return TN_EINVAL;
+  if (plan->B == 0) return TN_OK;
+  Bucket& b = plan->buckets[i];
+  if (!persistent) return launch_bucket(*plan, b, obs, obs_genome_stride, out, nullptr, stream);
+  b.grid = persistent_grid(*plan, b);
+  if (b.grid <= 0) return TN_EHIP;
+  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, stream, plan->d_counters + i, 1);
+  rc = tn::check_launch();
+  if (rc != TN_OK) return rc;
+  return launch_bucket(*plan, b, obs, obs_genome_stride, out, plan->d_counters + i, stream);
+}
+
 int tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
                  const char* tune_cache, hipStream_t stream) {
   int rc = check_plan_call(plan, obs, obs_genome_stride, out);

@@ -133,3 +133,15 @@ def test_full_batching_workload_sampled():
     assert np.array_equal(_bits(a), _bits(b))
     sample = np.random.default_rng(2).choice(pop.P, 12, replace=False).tolist()
     check(pop, obs, host(a), sample)
+
+
+def test_buckets_one_by_one_rebuild_the_outputs():
+    tn, pop, dp, tr, obs = _setup(350, 90)
+    xt = tensor(obs)
+    plan = tn.Plan(dp, tr, 90)
+    ref = _bits(tn.forward(dp, tr, xt))
+    for persistent in (True, False):
+        out = torch.full((pop.P, 90, pop.n_out), float("nan"), device="cuda")
+        for i in range(len(plan.buckets())):
+            plan.forward_bucket(i, xt, out, persistent)
+        assert np.array_equal(_bits(out), ref), persistent
