@@ -171,10 +171,13 @@ def batching(torch, tn, synth, args):
     eng = {1: "lds", 2: "register"}
     kern = ("forward_reg_queue_kernel" if buckets[dom]["engine"] == 2
             else "forward_queue_kernel")
+    traffic = recorded_traffic(eng[buckets[dom]["engine"]], buckets[dom]["obs_per_lane"],
+                               buckets[dom]["rows_class"])
     roofline = {"bound": "hbm", "kernel": f"{kern} (bucket {dom}: "
-                f"{eng[buckets[dom]['engine']]} engine, rows <= {buckets[dom]['rows_class']})",
+                f"{eng[buckets[dom]['engine']]} engine, {buckets[dom]['obs_per_lane']} obs per "
+                f"lane, rows <= {buckets[dom]['rows_class']})",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes": bucket_bytes[dom], "avg_ms": bucket_ms[dom]}
     passes = pop.P * B
     info = {
@@ -195,6 +198,29 @@ def batching(torch, tn, synth, args):
                     for b, m, by in zip(buckets, bucket_ms, bucket_bytes)],
     }
     return res, pop, obs_np
+
+
+def recorded_traffic(engine, obs_per_lane, rows_class):
+    """HBM bytes per launch of a bucket kernel from a committed rocprofv3 summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), if one matches this bucket and
+    the kernel's sources are unchanged since it was taken; else None."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if (rec.get("workload"), rec.get("engine"), rec.get("obs_per_lane"),
+                rec.get("rows_class")) != ("batching", engine, obs_per_lane, rows_class):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["sources_sha256"]:
+            return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def bucket_members(pop, tr, buckets):
