@@ -30,7 +30,7 @@ struct FwdArgs {
   float scale, offset;
   int n_tiles;   // tiles of 64*K observations per genome
   int n_groups;  // workgroups per genome
-  int per_wg;    // consecutive tiles per workgroup
+  int per_wg;    // grid form: consecutive tiles per workgroup; persistent: genomes per grab
   int rows;      // value rows per tile in LDS (>= every genome's n_rows)
   int skip_le;   // genomes with prog_rows <= skip_le are left to another launch (-1: none)
   const int32_t* genomes;  // genome list (nullptr: every genome, in order)
@@ -89,7 +89,7 @@ __device__ __forceinline__ void lds_genome(
   __shared__ float part[16];
   constexpr int kTile = kWave * K;
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int W = blockDim.x / kWave;
   const int T = blockDim.x;
   const int I = pop.n_in, O = pop.n_out, nio = I + O;
@@ -301,19 +301,21 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(TN_FWD_PARAMS) {
   lds_genome<K, kLoss, kProgLds>(TN_FWD_ARGS, g, t_begin, t_end);
 }
 
-// Persistent form: each workgroup takes the next genome of the list (longest
-// first) from a counter until the list is exhausted; the counter must be 0 at
-// launch.
+// Persistent form: each workgroup takes the next per_wg genomes of the list
+// (longest first) from a counter, one atomic per grab, until the list is
+// exhausted; the counter must be 0 at launch.
 template <int K, bool kProgLds>
 __global__ __launch_bounds__(kWave * 8) void forward_queue_kernel(TN_FWD_PARAMS) {
   __shared__ int item_sh;
   for (;;) {
-    if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, 1);
+    if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, a.per_wg);
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(item_sh);
     __syncthreads();
     if (item >= a.n_items) break;
-    lds_genome<K, false, kProgLds>(TN_FWD_ARGS, a.genomes[item], 0, a.n_tiles);
+    const int end = min(item + a.per_wg, a.n_items);
+    for (int i = item; i < end; ++i)
+      lds_genome<K, false, kProgLds>(TN_FWD_ARGS, a.genomes[i], 0, a.n_tiles);
   }
 }
 
@@ -435,7 +437,9 @@ int launch_forward(const tn_population& p, const tn_transformed& t, const float*
   FwdArgs a{obs_stride, B,   0,     0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.skip_le,
             work.genomes, work.queue, n_list};
   int grid = work.grid;
-  if (!work.queue) {
+  if (work.queue) {
+    a.per_wg = std::max(1, n_list / (4 * std::max(1, grid)));  // about 4 grabs per workgroup
+  } else {
     // enough workgroups to fill the chip; each takes consecutive tiles of a genome
     const int want = std::max(1, std::min(n_tiles, (2048 + n_list - 1) / std::max(1, n_list)));
     a.per_wg = (n_tiles + want - 1) / want;

@@ -28,7 +28,7 @@ struct RegArgs {
   float scale, offset;
   int n_tiles;     // tiles of 64 observations per genome
   int n_groups;    // tile chunks per list entry (grid form without loss)
-  int per_wave;    // tiles per chunk (grid form without loss)
+  int per_wave;    // grid form: tiles per chunk; persistent: items per wavefront per grab
   int rows;        // value rows in registers: 32 or 64
   int rows_lo;     // genomes with prog_rows <= rows_lo are left to another launch (-1: none)
   int skip_above;  // genomes needing more than `rows` rows are left to another launch
@@ -40,7 +40,7 @@ struct RegArgs {
 // Observations and outputs pass through LDS in chunks of up to kChunk
 // components per observation; a row of the chunk has an odd stride, so the
 // per-lane row accesses are free of bank conflicts.
-constexpr int kChunk = 32;
+constexpr int kChunk = 8;
 constexpr int kStage = kWave * (kChunk + 1);  // floats per wavefront
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
   extern __shared__ __align__(16) float stage_all[];
   __shared__ float part[8];
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int W = blockDim.x / kWave;
   float* stg = stage_all + wave * kStage;
   int entry, t_begin, t_end, t_step;
@@ -214,22 +214,30 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
   }
 }
 
-// Persistent form: every wavefront takes the next (list entry, tile) item from
-// a counter until the items are exhausted (list entries are ordered longest
-// first); the counter must be 0 at launch.
+// Persistent form: the workgroup takes the next W * chunk (list entry, tile)
+// items from a counter (one atomic per grab: a single counter serialises its
+// atomics) and wavefront w runs items base + w, base + w + W, ...; list entries
+// are ordered longest first. The counter must be 0 at launch.
 template <int NB>
 __global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PARAMS) {
   extern __shared__ __align__(16) float stage_all[];
-  const int lane = lane_id();
-  float* stg = stage_all + (threadIdx.x / kWave) * kStage;
+  __shared__ int base_sh;
+  const int wave = wave_id();
+  const int W = blockDim.x / kWave;
+  float* stg = stage_all + wave * kStage;
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(a.queue, 1);
-    item = __builtin_amdgcn_readfirstlane(item);  // uniform: keeps the program on scalar loads
-    if (item >= a.n_items) break;
-    const int e = item / a.n_tiles, t = item - e * a.n_tiles;
-    int st;
-    reg_genome<NB, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
+    __syncthreads();
+    const int base = __builtin_amdgcn_readfirstlane(base_sh);  // uniform: scalar program loads
+    __syncthreads();
+    if (base >= a.n_items) break;
+    for (int c = 0; c < a.per_wave; ++c) {
+      const int item = base + c * W + wave;
+      if (item >= a.n_items) break;
+      const int e = item / a.n_tiles, t = item - e * a.n_tiles;
+      int st;
+      reg_genome<NB, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+    }
   }
 }
 
@@ -276,6 +284,8 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
             tile.skip_above ? 1 : 0, work.genomes, work.queue, 0};
   if (work.queue) {
     a.n_items = n_list * n_tiles;
+    // items per wavefront per grab: about 4 grabs per resident workgroup
+    a.per_wave = std::max(1, (int)((int64_t)a.n_items / (4LL * waves * std::max(1, work.grid))));
     switch (tile.banks) {
       case 1: return launch_queue<1>(p, t, obs, out, a, work.grid, waves, stream);
       case 2: return launch_queue<2>(p, t, obs, out, a, work.grid, waves, stream);

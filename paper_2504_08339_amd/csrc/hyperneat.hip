@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void cppn_query_kernel(
     int n_chunks, int per_wave, uint16_t* __restrict__ w1t, uint16_t* __restrict__ w2t,
     float* __restrict__ raw1, float* __restrict__ raw2) {
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int W = blockDim.x / kWave;
   const int g = blockIdx.x / n_chunks;
   const int chunk = blockIdx.x - g * n_chunks;
@@ -153,7 +153,7 @@ struct GemmArgs {
 template <bool kTanh>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs p) {
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_id();
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
   if (item >= p.n_items) return;  // wavefront-uniform; the kernel has no barrier
   const int per_g = p.m_tiles * p.n_tiles;

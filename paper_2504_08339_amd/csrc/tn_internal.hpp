@@ -95,6 +95,14 @@ constexpr uint32_t kFnInput = 0x80000000u;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Index of this wavefront in its workgroup, as a wavefront-uniform value (the
+// compiler cannot see that threadIdx.x / 64 is uniform; anything derived from
+// it would otherwise leave the scalar unit: vector loads of the program,
+// indexed register reads through a per-lane loop).
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
 // Number of set bits of `mask` in lanes below this one.
 __device__ __forceinline__ int mbcnt(uint64_t mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
