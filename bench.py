@@ -18,7 +18,8 @@ Beside it (`workloads`), each with its own timed steps and roofline:
   differentiation  4096 genomes 4 -> 2, 1024 shared samples: forward + adjoint
                    with the fused MSE loss;
   hyperneat        1000 CPPNs on a 32x32 / 32x32 / 8 grid substrate, 128 obs per
-                   genome: CPPN query + substrate forward + substrate backward.
+                   genome: CPPN query + substrate forward + substrate backward +
+                   CPPN adjoint.
 
 `value` is genome-forward passes per second (P * B per step / time per step).
 The roofline object is for the dominant kernel of the headline step: every
@@ -355,7 +356,8 @@ def hyperneat(torch, tn, synth, args):
     def step(t):
         w1t, w2t = t("cppn_query", tn.cppn_query, dp, tr, grid, n_out, 0.2)
         h, y = t("substrate_forward", tn.substrate_forward, w1t, w2t, xb, grid, n_out)
-        t("substrate_backward", tn.substrate_backward, w2t, xb, h, dy, grid, n_out)
+        dw1t, dw2t = t("substrate_backward", tn.substrate_backward, w2t, xb, h, dy, grid, n_out)
+        t("cppn_backward", tn.cppn_backward, dp, tr, dw1t, dw2t, grid, n_out)
         state["w"] = (w1t, w2t)
     steps = max(2, args.steps // 4)
     step_ms, ms = timed_steps(torch, step, steps, 1)
@@ -366,7 +368,7 @@ def hyperneat(torch, tn, synth, args):
         "workload": "hyperneat: 1000 CPPNs 5 -> 1 (N_max 32, C_max 96) queried on a 32x32 / "
                     "32x32 / 8 grid substrate (1,056,768 queries each), |w| < 0.2 -> 0, bf16; "
                     "128 N(0,1) bf16 inputs per genome; step = query + substrate forward + "
-                    "substrate backward",
+                    "substrate backward + CPPN adjoint",
         "ms_per_step": step_ms, "call_ms": ms, "steps": steps,
         "queries_per_s": pop.P * (S * S + S * n_out) / (ms["cppn_query"] * 1e-3),
         "substrate_forward": {

@@ -419,6 +419,25 @@ int tn_substrate_backward(const tn_substrate* sub, int32_t P, const uint16_t* w2
                           const float* dy, void* workspace, float* dw1t, float* dw2t,
                           hipStream_t stream);
 
+/* Gradient with respect to the CPPN genomes' connection weights and node
+ * biases of L = sum over every substrate connection of u * w, where w is the
+ * weight tn_cppn_query produced and the upstream u is dw1t[g][t][s] (input s
+ * -> hidden t) or dw2t[g][j][s] (hidden s -> output j) when the CPPN value
+ * survived the threshold, 0 otherwise (with dw1t, dw2t from
+ * tn_substrate_backward this is the gradient of the substrate loss through the
+ * whole encoding). The threshold decision is this call's own float32 CPPN
+ * value, the same one tn_cppn_query thresholds. dW shaped like
+ * pop->conn_w and db like pop->node_bias; disabled, padding and input rows get
+ * 0; genomes that are flagged, have more than 32 nodes or 64 enabled
+ * connections, or use an aggregation other than sum or mean get NaN.
+ * Per-query terms are accumulated in float32 per lane and reduced in a fixed
+ * order (deterministic). workspace: tn_cppn_backward_workspace_size bytes. */
+int tn_cppn_backward_workspace_size(const tn_population* pop, const tn_substrate* sub,
+                                    size_t* bytes);
+int tn_cppn_backward(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,
+                     const float* dw1t, const float* dw2t, void* workspace, float* dW,
+                     float* db, hipStream_t stream);
+
 /* ---------------------------------------------------------- gradients */
 
 /*

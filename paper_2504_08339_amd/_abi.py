@@ -119,6 +119,11 @@ SIGNATURES = {
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                              ctypes.c_int32, c_float_p, c_float_p,
                                              ctypes.c_void_p, c_float_p, c_float_p, _STREAM]),
+    "tn_cppn_backward_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(TnSubstrate),
+                                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_cppn_backward": (ctypes.c_int, [_POP, _TR, ctypes.POINTER(TnSubstrate), c_float_p,
+                                        c_float_p, ctypes.c_void_p, c_float_p, c_float_p,
+                                        _STREAM]),
     "tn_substrate_forward": (ctypes.c_int, [ctypes.POINTER(TnSubstrate), ctypes.c_int32,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_int32, c_float_p, c_float_p,

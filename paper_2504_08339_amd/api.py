@@ -390,3 +390,25 @@ def substrate_backward(w2t: torch.Tensor, x: torch.Tensor, h: torch.Tensor, dy: 
         stride, B, _p(h, _abi.c_float_p), _p(dy, _abi.c_float_p), ctypes.c_void_p(ws.data_ptr()),
         _p(dw1t, _abi.c_float_p), _p(dw2t, _abi.c_float_p), _stream(x.device)))
     return dw1t, dw2t
+
+
+def cppn_backward(pop: Population, tr: Transformed, dw1t: torch.Tensor, dw2t: torch.Tensor,
+                  grid: int = 32, n_out: int = 8, threshold: float = 0.2):
+    """(dW, db) shaped like conn_w / node_bias: gradient of sum(dw * w) over every
+    substrate weight the CPPNs produce, through the weights that survived the
+    threshold (dw1t [P][S][S], dw2t [P][n_out][S] float32, as from
+    substrate_backward)."""
+    sub = _substrate(grid, n_out, threshold)
+    for t in (dw1t, dw2t):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("dw1t and dw2t must be contiguous float32 tensors")
+    n = ctypes.c_size_t()
+    _check("tn_cppn_backward_workspace_size", _lib.tn_cppn_backward_workspace_size(
+        ctypes.byref(pop.c), ctypes.byref(sub), ctypes.byref(n)))
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=pop.device)
+    dW, db = _grad_buffers(pop)
+    _check("tn_cppn_backward", _lib.tn_cppn_backward(
+        ctypes.byref(pop.c), ctypes.byref(tr.c), ctypes.byref(sub), _p(dw1t, _abi.c_float_p),
+        _p(dw2t, _abi.c_float_p), ctypes.c_void_p(ws.data_ptr()), _p(dW, _abi.c_float_p),
+        _p(db, _abi.c_float_p), _stream(pop.device)))
+    return dW, db

@@ -28,6 +28,10 @@ int launch_substrate_backward(const tn_substrate& sub, int P, const uint16_t* w2
                               const uint16_t* x, int64_t x_stride, int B, const float* h,
                               const float* dy, void* workspace, float* dw1t, float* dw2t,
                               hipStream_t stream);
+size_t cppn_backward_workspace_bytes(const tn_population& p, const tn_substrate& sub);
+int launch_cppn_backward(const tn_population& p, const tn_transformed& t, const tn_substrate& sub,
+                         const float* dw1t, const float* dw2t, void* workspace, float* dW,
+                         float* db, hipStream_t stream);
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
@@ -346,6 +350,32 @@ int tn_substrate_backward(const tn_substrate* sub, int32_t P, const uint16_t* w2
   if (!w2t || !x || !h || !dy || !workspace || !dw1t || !dw2t) return TN_EINVAL;
   return launch_substrate_backward(*sub, P, w2t, x, x_genome_stride, B, h, dy, workspace, dw1t,
                                    dw2t, stream);
+}
+
+int tn_cppn_backward_workspace_size(const tn_population* pop, const tn_substrate* sub,
+                                    size_t* bytes) {
+  if (!bytes) return TN_EINVAL;
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  *bytes = cppn_backward_workspace_bytes(*pop, *sub);
+  return TN_OK;
+}
+
+int tn_cppn_backward(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,
+                     const float* dw1t, const float* dw2t, void* workspace, float* dW,
+                     float* db, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  rc = check_substrate(sub);
+  if (rc != TN_OK) return rc;
+  if (pop->n_in != 5 || pop->n_out != 1) return TN_ESHAPE;
+  if (pop->P == 0) return TN_OK;
+  rc = check_transformed(tr);
+  if (rc != TN_OK) return rc;
+  if (!dw1t || !dw2t || !workspace || !dW || !db) return TN_EINVAL;
+  return launch_cppn_backward(*pop, *tr, *sub, dw1t, dw2t, workspace, dW, db, stream);
 }
 
 }  // extern "C"

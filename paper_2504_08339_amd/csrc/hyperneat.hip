@@ -316,6 +316,197 @@ __global__ __launch_bounds__(256) void transpose_x_kernel(const uint16_t* __rest
   }
 }
 
+// ----------------------------------------------------------- CPPN adjoint
+
+// Limits of the CPPN adjoint: node values and per-lane gradient accumulators
+// live in registers, indexed by topological position (no row reuse: the
+// reverse sweep needs every value).
+constexpr int kCppnNodes = 32, kCppnEdges = 64;
+constexpr int kCppnPart = kCppnEdges + kCppnNodes;  // partial sums per wavefront
+
+__device__ __forceinline__ float bget(const f32x32& b, int i) { return b[i]; }
+__device__ __forceinline__ void bset(f32x32& b, int i, float x) { b[i] = x; }
+
+__device__ __forceinline__ float cppn_slope(int act, float v, float z) {
+  switch (act) {
+    case TN_ACT_IDENTITY: return 1.0f;
+    case TN_ACT_SIGMOID: return v * (1.0f - v);
+    case TN_ACT_TANH: return fmaf(-v, v, 1.0f);
+    case TN_ACT_RELU: return v > 0.0f ? 1.0f : 0.0f;
+    case TN_ACT_SIN: return cosf(z);
+    case TN_ACT_GAUSSIAN: return -2.0f * z * v;
+    default: return z > 0.0f ? 1.0f : (z < 0.0f ? -1.0f : 0.0f);  // abs
+  }
+}
+
+// The gradient of sum_q u_q * w(q) over every query q of the substrate with
+// respect to the CPPN's connection weights and node biases, where the upstream
+// u_q is dw1t / dw2t at the query when its weight survived the threshold (the
+// CPPN value of this very evaluation, float32) and 0 otherwise. Each lane runs
+// the CPPN forward at its query (values and pre-activations kept by position),
+// then the reverse sweep:
+//   delta_k = gbar_k act'(z_k);  db_k += delta_k;
+//   for in-edge e = (j -> k): dt = delta_k rho_k (/ n for mean);
+//   dw_e += dt v_j;  gbar_j += dt w_e
+// accumulating over all its queries; at the end every sum is reduced over the
+// wavefront and written to this wavefront's slot of `part`. Sum and mean
+// aggregation only (the CPPN's); other genomes get NaN.
+__global__ __launch_bounds__(256) void cppn_backward_kernel(
+    PopView pop, const int32_t* __restrict__ status, const int32_t* __restrict__ n_valid,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ edge_src,
+    const int32_t* __restrict__ w_bits, const int32_t* __restrict__ fn,
+    const int32_t* __restrict__ bias_bits, const int32_t* __restrict__ resp_bits,
+    const int32_t* __restrict__ io_pos, SubGeom sg, int n_chunks, int per_wave,
+    const float* __restrict__ dw1t, const float* __restrict__ dw2t, float* __restrict__ part) {
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int W = blockDim.x / kWave;
+  const int g = blockIdx.x / n_chunks;
+  const int chunk = blockIdx.x - g * n_chunks;
+  float* out = part + ((int64_t)g * n_chunks * W + (int64_t)chunk * W + wave) * kCppnPart;
+  const int n = n_valid[g];
+  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
+  const int32_t* rp = row_ptr + rb;
+  const int n_edges = n > 0 ? rp[n] : 0;
+  const int nio = pop.n_in + pop.n_out;
+  const int op = status[g] ? 0 : io_pos[(int64_t)g * nio + pop.n_in];
+  bool ok = status[g] == 0 && n <= kCppnNodes && n_edges <= kCppnEdges;
+  for (int p = 0; ok && p < n; ++p) {
+    const int f = fn[nb + p];
+    const int agg = (f >> 8) & 0xff;
+    if (f >= 0 && agg != TN_AGG_SUM && agg != TN_AGG_MEAN) ok = false;
+  }
+  if (!ok) {
+    for (int i = lane; i < kCppnPart; i += kWave) out[i] = __builtin_nanf("");
+    return;
+  }
+  const int32_t* fnp = fn + nb;
+  const int32_t* bp = bias_bits + nb;
+  const int32_t* rsp = resp_bits + nb;
+  const int32_t* srcp = edge_src + cb;
+  const int32_t* wp = w_bits + cb;
+  const int Q1 = sg.S * sg.S, Q = Q1 + sg.S * sg.n_out;
+  const int n_tiles = (Q + kWave - 1) / kWave;
+  const int t0 = (chunk * W + wave) * per_wave;
+  const int t1 = min(t0 + per_wave, n_tiles);
+  f32x32 acc_db = 0.0f, acc_w0 = 0.0f, acc_w1 = 0.0f;
+  for (int t = t0; t < t1; ++t) {
+    const int q = t * kWave + lane;
+    const bool live = q < Q;
+    const bool first = q < Q1;
+    const int qq = first ? q : q - Q1;
+    const int tgt = qq / sg.S;
+    const int src = qq - tgt * sg.S;
+    const int rs = src / sg.grid, cs = src - rs * sg.grid;
+    float in[5];
+    in[0] = fmaf((float)cs, sg.step, -1.0f);
+    in[1] = fmaf((float)rs, sg.step, -1.0f);
+    if (first) {
+      const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
+      in[2] = fmaf((float)ct, sg.step, -1.0f);
+      in[3] = fmaf((float)rt, sg.step, -1.0f);
+    } else {
+      in[2] = sg.n_out > 1 ? fmaf((float)tgt, sg.ostep, -1.0f) : 0.0f;
+      in[3] = 0.0f;
+    }
+    in[4] = 1.0f;
+    const float up = live ? (first ? dw1t[(int64_t)g * Q1 + qq]
+                                   : dw2t[(int64_t)g * sg.S * sg.n_out + qq])
+                          : 0.0f;
+    // forward, values and pre-activations by position
+    f32x32 v = 0.0f, z = 0.0f;
+    asm volatile("" : "+v"(v), "+v"(z));
+    for (int p = 0; p < n; ++p) {
+      const int f = fnp[p];
+      if (f < 0) {
+        const int k = (f >> 16) & 0x7fff;
+        const float x = k == 0 ? in[0] : k == 1 ? in[1] : k == 2 ? in[2] : k == 3 ? in[3] : in[4];
+        bset(v, p, x);
+        continue;
+      }
+      const int e0 = rp[p], e1 = rp[p + 1];
+      float sum = 0.0f;
+      for (int e = e0; e < e1; ++e) sum = fmaf(__int_as_float(wp[e]), bget(v, srcp[e]), sum);
+      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) sum = sum / (float)(e1 - e0);
+      const float zz[1] = {fmaf(__int_as_float(rsp[p]), sum, __int_as_float(bp[p]))};
+      float vv[1];
+      activate_all<1>(f & 0xff, zz, vv);
+      bset(v, p, vv[0]);
+      bset(z, p, zz[0]);
+    }
+    const float y = bget(v, op);
+    const float u = fabsf(y) >= sg.thr ? up : 0.0f;  // NaN y: no gradient
+    // reverse sweep
+    f32x32 gb = 0.0f;
+    asm volatile("" : "+v"(gb));
+    bset(gb, op, u);
+    for (int p = n - 1; p >= 0; --p) {
+      const int f = fnp[p];
+      if (f < 0) continue;
+      const float delta = bget(gb, p) * cppn_slope(f & 0xff, bget(v, p), bget(z, p));
+      bset(acc_db, p, bget(acc_db, p) + delta);
+      const int e0 = rp[p], e1 = rp[p + 1];
+      float dt = delta * __int_as_float(rsp[p]);
+      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) dt = dt / (float)(e1 - e0);
+      for (int e = e0; e < e1; ++e) {
+        const int j = srcp[e];
+        if (e < 32)
+          bset(acc_w0, e, fmaf(dt, bget(v, j), bget(acc_w0, e)));
+        else
+          bset(acc_w1, e - 32, fmaf(dt, bget(v, j), bget(acc_w1, e - 32)));
+        bset(gb, j, fmaf(dt, __int_as_float(wp[e]), bget(gb, j)));
+      }
+    }
+  }
+  // one reduction over the wavefront per sum, fixed order
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    const float a0 = wave_sum(acc_w0[e]);
+    const float a1 = wave_sum(acc_w1[e]);
+    if (lane == 0) {
+      out[e] = a0;
+      out[32 + e] = a1;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 32; ++p) {
+    const float d = wave_sum(acc_db[p]);
+    if (lane == 0) out[kCppnEdges + p] = d;
+  }
+}
+
+// Sums the wavefront partials of each genome in slot order and scatters them:
+// dW[connection row of in-edge e], db[node row of position p]; every other row
+// of the genome (disabled, padding, inputs) is 0; NaN where the partials are.
+__global__ __launch_bounds__(256) void cppn_grad_reduce_kernel(
+    PopView pop, const int32_t* __restrict__ n_valid, const int32_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ edge_row, const int32_t* __restrict__ order,
+    const int32_t* __restrict__ fn, const float* __restrict__ part, int slots,
+    float* __restrict__ dW, float* __restrict__ db) {
+  const int g = blockIdx.x;
+  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
+  const int nrows = (int)pop.node_rows(g), crows = (int)pop.conn_rows(g);
+  const int n = n_valid[g];
+  const int n_edges = n > 0 ? row_ptr[rb + n] : 0;
+  const float* pg = part + (int64_t)g * slots * kCppnPart;
+  const bool bad = n == 0 || pg[0] != pg[0] || n > kCppnNodes || n_edges > kCppnEdges;
+  for (int r = threadIdx.x; r < crows; r += blockDim.x) dW[cb + r] = bad ? __builtin_nanf("") : 0.0f;
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) db[nb + r] = bad ? __builtin_nanf("") : 0.0f;
+  __syncthreads();
+  if (bad) return;
+  for (int i = threadIdx.x; i < n_edges + n; i += blockDim.x) {
+    const int col = i < n_edges ? i : kCppnEdges + (i - n_edges);
+    float acc = 0.0f;
+    for (int w = 0; w < slots; ++w) acc += pg[(int64_t)w * kCppnPart + col];
+    if (i < n_edges) {
+      dW[cb + edge_row[cb + i]] = acc;
+    } else {
+      const int p = i - n_edges;
+      if (fn[nb + p] >= 0) db[nb + order[nb + p]] = acc;
+    }
+  }
+}
+
 }  // namespace
 
 int check_substrate(const tn_substrate* sub) {
@@ -424,6 +615,50 @@ int launch_substrate_backward(const tn_substrate& sub, int P, const uint16_t* w2
   ga.N = S;
   ga.K = Kp;
   return launch_gemm<false>(ga, P, stream);
+}
+
+namespace {
+constexpr int kCppnWaves = 4, kCppnTilesPerWave = 64;
+
+int cppn_chunks(const tn_substrate& sub) {
+  const int64_t S = (int64_t)sub.grid * sub.grid;
+  const int64_t n_tiles = (S * S + S * sub.n_out + kWave - 1) / kWave;
+  const int64_t per_wg = (int64_t)kCppnWaves * kCppnTilesPerWave;
+  return (int)((n_tiles + per_wg - 1) / per_wg);
+}
+}  // namespace
+
+size_t cppn_backward_workspace_bytes(const tn_population& p, const tn_substrate& sub) {
+  return sizeof(float) * (size_t)p.P * cppn_chunks(sub) * kCppnWaves * kCppnPart;
+}
+
+int launch_cppn_backward(const tn_population& p, const tn_transformed& t, const tn_substrate& sub,
+                         const float* dw1t, const float* dw2t, void* workspace, float* dW,
+                         float* db, hipStream_t stream) {
+  SubGeom sg;
+  sg.grid = sub.grid;
+  sg.S = sub.grid * sub.grid;
+  sg.n_out = sub.n_out;
+  sg.thr = sub.threshold;
+  sg.step = 2.0f / (float)(sub.grid - 1);
+  sg.ostep = sub.n_out > 1 ? 2.0f / (float)(sub.n_out - 1) : 0.0f;
+  const int n_chunks = cppn_chunks(sub);
+  const int64_t grid = (int64_t)p.P * n_chunks;
+  if (grid == 0) return TN_OK;
+  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
+  float* part = static_cast<float*>(workspace);
+  hipLaunchKernelGGL(cppn_backward_kernel, dim3((unsigned)grid), dim3(kWave * kCppnWaves), 0,
+                     stream, make_view(p), t.status, t.n_valid, t.row_ptr, t.edge_src,
+                     reinterpret_cast<const int32_t*>(t.edge_w), t.pos_fn,
+                     reinterpret_cast<const int32_t*>(t.pos_bias),
+                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, sg, n_chunks,
+                     kCppnTilesPerWave, dw1t, dw2t, part);
+  int rc = check_launch();
+  if (rc != TN_OK) return rc;
+  hipLaunchKernelGGL(cppn_grad_reduce_kernel, dim3((unsigned)p.P), dim3(256), 0, stream,
+                     make_view(p), t.n_valid, t.row_ptr, t.edge_row, t.order, t.pos_fn, part,
+                     n_chunks * kCppnWaves, dW, db);
+  return check_launch();
 }
 
 }  // namespace tn

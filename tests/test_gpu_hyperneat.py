@@ -109,6 +109,11 @@ def test_cppn_query_flagged_and_shape_errors():
     xor = to_device(synth.xor_population(P=2))
     with pytest.raises(tn.TNError):
         tn.cppn_query(xor, tn.transform(xor), 8, 2, THR)   # not a 5 -> 1 CPPN
+    u1 = torch.zeros((2, 64, 64), device="cuda")
+    u2 = torch.zeros((2, 2, 64), device="cuda")
+    dW, db = tn.cppn_backward(dp, tr, u1, u2, 8, 2, THR)
+    assert np.isnan(host(dW)[1]).all() and np.isnan(host(db)[1]).all()
+    assert np.all(host(dW)[0] == 0.0) and np.all(host(db)[0] == 0.0)
 
 
 def _substrate_case(P, B, shared):
@@ -219,3 +224,76 @@ def test_substrate_backward_matches_oracle(shared):
         dZ = (dY @ W2[g]) * (1.0 - H * H)
         b1 = 2.0 ** -8 * (np.abs(Xg).T @ np.abs(dZ)) + 1e-30            # [s][t]
         assert np.all(np.abs(dw1t[g].T - dW1) <= b1), g
+
+
+def _cppn_grad_case(grid, n_out, P, seed):
+    import paper_2504_08339_amd as tn
+    pop = synth.cppn_population(seed=seed, P=P)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
+    S = grid * grid
+    rng = np.random.default_rng(seed)
+    u1 = rng.standard_normal((P, S, S)).astype(np.float32)
+    u2 = rng.standard_normal((P, n_out, S)).astype(np.float32)
+    dW, db = tn.cppn_backward(dp, tr, torch.from_numpy(u1).cuda(), torch.from_numpy(u2).cuda(),
+                              grid, n_out, THR)
+    return pop, host(r1), host(r2), u1, u2, host(dW), host(db)
+
+
+def _check_cppn_grads(pop, grid, n_out, r1, r2, u1, u2, dW, db, genomes):
+    """Against the oracle's CPPN adjoint with the GPU's threshold decisions:
+    |g - g_ref| <= 1e-4 |g_ref| + 1e-5 max|g_ref| per genome (float32 sums
+    over up to 2^20 queries of terms that carry the forward's 1e-5 error)."""
+    src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    for g in genomes:
+        gen = oracle.decode(pop, g)
+        tr = oracle.transform(gen)
+        if tr.status:
+            assert np.isnan(dW[g]).all() and np.isnan(db[g]).all()
+            continue
+        a = hn.cppn_gradient(gen, tr, src, src, r1[g].T, u1[g].T.astype(np.float64))
+        b = hn.cppn_gradient(gen, tr, src, outs, r2[g].T, u2[g].T.astype(np.float64))
+        ref_w = np.zeros(pop.C_max)
+        ref_b = np.zeros(pop.N_max)
+        for row, val in a[0].items():
+            ref_w[row] += val + b[0][row]
+        for row, val in a[1].items():
+            ref_b[row] += val + b[1][row]
+        ref = np.concatenate([ref_w, ref_b])
+        got = np.concatenate([dW[g], db[g]]).astype(np.float64)
+        tol = 1e-4 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+        assert np.all(np.abs(got - ref) <= tol), (g, float(np.max(np.abs(got - ref) - tol)))
+
+
+def test_cppn_backward_small_grid():
+    pop, r1, r2, u1, u2, dW, db = _cppn_grad_case(8, 2, 8, 31)
+    _check_cppn_grads(pop, 8, 2, r1, r2, u1, u2, dW, db, range(pop.P))
+    dead = (pop.conn_in < 0) | (pop.conn_en == 0)
+    assert np.all(dW[dead] == 0.0)
+    assert np.all(db[pop.node_key < pop.n_in] == 0.0)
+
+
+def test_cppn_backward_full_substrate():
+    pop, r1, r2, u1, u2, dW, db = _cppn_grad_case(GRID, NOUT, 2, 41)
+    _check_cppn_grads(pop, GRID, NOUT, r1, r2, u1, u2, dW, db, range(pop.P))
+
+
+def test_cppn_backward_through_the_substrate():
+    """The whole chain: CPPN query -> substrate forward -> substrate backward ->
+    CPPN adjoint, against the oracle's pipeline gradient (with the GPU's
+    threshold decisions and the GPU's substrate gradients as upstream)."""
+    import paper_2504_08339_amd as tn
+    pop = synth.cppn_population(seed=51, P=2)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    grid, n_out = 8, 4
+    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
+    rng = np.random.default_rng(6)
+    xb = torch.from_numpy(rng.standard_normal((32, grid * grid)).astype(np.float32)).cuda().to(torch.bfloat16)
+    h, y = tn.substrate_forward(w1t, w2t, xb, grid, n_out)
+    dy = torch.from_numpy(rng.standard_normal((2, 32, n_out)).astype(np.float32)).cuda()
+    dw1t, dw2t = tn.substrate_backward(w2t, xb, h, dy, grid, n_out)
+    dW, db = tn.cppn_backward(dp, tr, dw1t, dw2t, grid, n_out)
+    _check_cppn_grads(pop, grid, n_out, host(r1), host(r2), host(dw1t), host(dw2t), host(dW),
+                      host(db), range(pop.P))
