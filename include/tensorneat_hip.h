@@ -302,7 +302,7 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
 /*
  * Batched forward pass of a population whose genomes differ widely in size
  * (the space-time trade-off of the padded encoding, Section 3.3; the
- * population-level parallelism of Section 3.4). A plan sorts the genomes once
+ * population-level parallelism of Sections 4.1 and 5.4). A plan sorts the genomes once
  * into length buckets by the value rows their forward pass needs:
  *   prog_rows <= 32, <= 64       TN_ENGINE_REG (one / two register banks);
  *   n_rows <= 128, <= 256, <= the LDS capacity (about 600 rows on MI355X)
