@@ -147,7 +147,7 @@ def batching(torch, tn, synth, args):
     # 8 B per edge; LDS engine: row_ptr, level, fn, bias, resp, row 24 B per
     # position + 8 B per edge), plus the io positions
     prog_rows = tr.prog_rows.cpu().numpy()[:pop.P]
-    reg = prog_rows <= 64
+    reg = prog_rows + 1 <= 208
     per_genome = (4 * B * (I + O) + np.where(reg, 16 * nv, 24 * nv + 4) + 8 * ne
                   + 4 * (I + O) + 12)
     total_bytes = int(per_genome.sum())
@@ -225,22 +225,27 @@ def recorded_traffic(engine, obs_per_lane, rows_class):
 
 
 def bucket_members(pop, tr, buckets):
-    """Genome indices of each bucket, by the plan's documented rule."""
+    """Genome indices of each bucket, by the plan's documented rule: register
+    buckets by prog_rows + 1 (the register file's zero row; flagged genomes in
+    the first), LDS buckets by n_rows for the programs too large for the
+    largest register file."""
     import numpy as np
     st = tr.status.cpu().numpy()[:pop.P]
     pr = tr.prog_rows.cpu().numpy()[:pop.P]
     nr = tr.n_rows.cpu().numpy()[:pop.P]
-    lists, lo = [], None
+    reg_max = max(b["rows_class"] for b in buckets if b["engine"] == 2)
+    lists, lo_reg, lo_lds = [], 0, None
     for b in buckets:
-        if b["engine"] == 2 and b["rows_class"] == 32:
-            m = (st != 0) | (pr <= 32)
-        elif b["engine"] == 2:
-            m = (st == 0) & (pr > 32) & (pr <= 64)
+        if b["engine"] == 2:
+            m = (st == 0) & (pr + 1 > lo_reg) & (pr + 1 <= b["rows_class"])
+            if lo_reg == 0:
+                m |= st != 0
+            lo_reg = b["rows_class"]
         else:
-            m = (st == 0) & (pr > 64) & (nr <= b["rows_class"])
-            if lo is not None:
-                m &= nr > lo
-            lo = b["rows_class"]
+            m = (st == 0) & (pr + 1 > reg_max) & (nr <= b["rows_class"])
+            if lo_lds is not None:
+                m &= nr > lo_lds
+            lo_lds = b["rows_class"]
         lists.append(np.flatnonzero(m))
     return lists
 

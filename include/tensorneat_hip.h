@@ -188,9 +188,21 @@ int tn_validate_population(const tn_population* pop);
  *                        (whose prog row is its input index). Prog rows are
  *                        freed right after the last consumer has read them (it
  *                        may take one for its own value), outputs keep theirs.
- *   prog_edge conn block x 2 int32: {prog row of the source, bits of the weight}
+ *   prog_edge conn block x 2 int32: {prog row of the source, bits of the weight},
+ *                        followed by 8 padding entries after the whole array
+ *                        (2 * (conn_elems + 8) int32 in all: the register
+ *                        engine reads edges in groups of 8 ahead)
  *   prog_rows [P]        rows the packed program uses (the largest number of
  *                        values live at once; 0 for a flagged genome)
+ *   prog_rec node block x 16 int32: the packed program again, one record per
+ *                        non-input position in order (records past the last
+ *                        are 0): word 0 = act | agg << 3 | prog row << 6 |
+ *                        in-edge count << 17; word 1 bias bits; word 2
+ *                        response bits; word 3 = index (in the conn block of
+ *                        prog_edge) of the node's 7th in-edge; words 4..15 its
+ *                        first 6 in-edges as {source prog row, weight bits},
+ *                        unused slots {prog_rows, +0} (a row the engine keeps
+ *                        at +0, so they add nothing)
  */
 typedef struct tn_transformed {
     int32_t* status;
@@ -210,6 +222,7 @@ typedef struct tn_transformed {
     int32_t* prog_node;
     int32_t* prog_edge;
     int32_t* prog_rows;
+    int32_t* prog_rec;
 } tn_transformed;
 
 /* Element counts of the tn_transformed arrays for a population (host only):
@@ -260,13 +273,17 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr,
  *                  each level of the topological order among its wavefronts;
  *                  genomes whose n_rows exceeds `rows` get NaN outputs.
  *   TN_ENGINE_REG  each wavefront evaluates one genome on a tile of 64
- *                  observations with the values in registers (obs_per_lane 0
- *                  or 1; `rows` = 32 or 64, 0: 64); waves_per_genome (1..8)
- *                  wavefronts of one genome share a workgroup; genomes whose
- *                  prog_rows exceeds `rows` get NaN outputs.
+ *                  observations (obs_per_lane 0 or 1) walking the packed
+ *                  program, with the values in a register file of `rows`
+ *                  rows (32, 64, 96, 128, 160 or 208; 0: 64); waves_per_genome
+ *                  (1..8) wavefronts share a workgroup; genomes whose
+ *                  prog_rows + 1 (the program's rows and a zero row)
+ *                  exceeds `rows` get NaN outputs.
  *   TN_ENGINE_AUTO the library's choice for every genome (the other fields
- *                  are ignored): TN_ENGINE_REG for prog_rows <= 64,
- *                  TN_ENGINE_LDS with rows = N_max for the rest.
+ *                  are ignored): TN_ENGINE_REG for prog_rows < 208 (rows 64,
+ *                  then 208), TN_ENGINE_LDS with rows = min(N_max, the LDS
+ *                  capacity, about 600 rows on MI355X) for the rest; a genome
+ *                  needing more than that capacity gets NaN outputs.
  * Outputs are bitwise identical across engines and tile shapes. */
 enum tn_engine { TN_ENGINE_AUTO = 0, TN_ENGINE_LDS = 1, TN_ENGINE_REG = 2 };
 
@@ -304,9 +321,11 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
  * (the space-time trade-off of the padded encoding, Section 3.3; the
  * population-level parallelism of Sections 4.1 and 5.4). A plan sorts the genomes once
  * into length buckets by the value rows their forward pass needs:
- *   prog_rows <= 32, <= 64       TN_ENGINE_REG (one / two register banks);
- *   n_rows <= 128, <= 256, <= the LDS capacity (about 600 rows on MI355X)
- *                                TN_ENGINE_LDS.
+ *   prog_rows + 1 <= 32, 64, 96, 128, 160, 208   TN_ENGINE_REG with a
+ *                                             register file of that many
+ *                                             rows (one of them a zero row);
+ *   larger, n_rows <= 256, <= the LDS capacity (about 600 rows on MI355X)
+ *                                             TN_ENGINE_LDS.
  * Flagged genomes join the first bucket (NaN outputs). Each bucket lists its
  * genomes longest first (enabled edges + nodes).
  *
@@ -338,7 +357,7 @@ typedef struct tn_plan tn_plan;
 
 typedef struct tn_bucket_info {
     int32_t engine;       /* TN_ENGINE_REG or TN_ENGINE_LDS */
-    int32_t rows_class;   /* REG: 32 or 64; LDS: upper bound of n_rows */
+    int32_t rows_class;   /* REG: register-file rows (bound of prog_rows + 1); LDS: bound of n_rows */
     int32_t count;        /* genomes */
     int64_t edges;        /* enabled edges over the bucket */
     tn_tile tile;         /* current tile (rows: register rows / LDS rows) */

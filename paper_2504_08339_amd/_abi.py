@@ -44,7 +44,7 @@ class TnTransformed(ctypes.Structure):
         ("edge_w", c_float_p), ("pos_bias", c_float_p), ("pos_resp", c_float_p),
         ("pos_fn", c_int32_p), ("io_pos", c_int32_p), ("pos_row", c_int32_p),
         ("n_rows", c_int32_p), ("prog_node", c_int32_p), ("prog_edge", c_int32_p),
-        ("prog_rows", c_int32_p)]
+        ("prog_rows", c_int32_p), ("prog_rec", c_int32_p)]
 
 
 class TnTransformedElems(ctypes.Structure):

@@ -122,8 +122,9 @@ class Transformed:
         self.pos_row = torch.empty(max(sz.node_elems, 1), **i32)
         self.n_rows = torch.empty(max(sz.genome_elems, 1), **i32)
         self.prog_node = torch.empty(4 * max(sz.node_elems, 1), **i32)
-        self.prog_edge = torch.empty(2 * max(sz.conn_elems, 1), **i32)
+        self.prog_edge = torch.empty(2 * (max(sz.conn_elems, 1) + 8), **i32)  # + 8 padding
         self.prog_rows = torch.empty(max(sz.genome_elems, 1), **i32)
+        self.prog_rec = torch.empty(16 * max(sz.node_elems, 1), **i32)
         self.c = TnTransformed(*[_p(getattr(self, n), ty) for n, ty in (
             ("status", _abi.c_int32_p), ("n_valid", _abi.c_int32_p), ("order", _abi.c_int32_p),
             ("level", _abi.c_int32_p), ("row_ptr", _abi.c_int32_p), ("edge_src", _abi.c_int32_p),
@@ -131,7 +132,7 @@ class Transformed:
             ("pos_resp", _abi.c_float_p), ("pos_fn", _abi.c_int32_p), ("io_pos", _abi.c_int32_p),
             ("pos_row", _abi.c_int32_p), ("n_rows", _abi.c_int32_p),
             ("prog_node", _abi.c_int32_p), ("prog_edge", _abi.c_int32_p),
-            ("prog_rows", _abi.c_int32_p))])
+            ("prog_rows", _abi.c_int32_p), ("prog_rec", _abi.c_int32_p))])
 
 
 def transform(pop: Population, out: Optional[Transformed] = None) -> Transformed:

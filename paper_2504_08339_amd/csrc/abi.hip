@@ -94,7 +94,7 @@ int check_transformed(const tn_transformed* t) {
   if (!t) return TN_EINVAL;
   if (!t->status || !t->n_valid || !t->order || !t->level || !t->row_ptr || !t->edge_src ||
       !t->edge_row || !t->edge_w || !t->pos_bias || !t->pos_resp || !t->pos_fn || !t->io_pos ||
-      !t->pos_row || !t->n_rows || !t->prog_node || !t->prog_edge || !t->prog_rows)
+      !t->pos_row || !t->n_rows || !t->prog_node || !t->prog_edge || !t->prog_rows || !t->prog_rec)
     return TN_EINVAL;
   return TN_OK;
 }
@@ -157,18 +157,25 @@ int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t
 
 namespace {
 
-// TN_ENGINE_AUTO: registers for every genome whose packed program fits in 64
-// rows, the level-parallel LDS kernel for the rest (prog_rows <= N_max, so a
-// population with N_max <= 64 needs one launch).
+// TN_ENGINE_AUTO: the register engine for every genome whose packed program
+// (plus the engine's zero row) fits in 208 rows (a 64-row register file, then
+// a 208-row one for the larger programs), the level-parallel LDS engine for
+// the rest (prog_rows <= N_max, so small populations need fewer launches).
 int forward_auto(const tn_population& p, const tn_transformed& t, const float* obs,
                  int64_t stride, int B, float* out, hipStream_t stream) {
   tn::RegTile rt;
+  rt.rf = 64;
   rt.skip_above = p.N_max > 64;
   int rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
   if (rc != TN_OK || p.N_max <= 64) return rc;
+  rt.rf = 208;
+  rt.rows_lo = 64;
+  rt.skip_above = p.N_max > 208;
+  rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
+  if (rc != TN_OK || p.N_max <= 208) return rc;
   tn::LdsTile lt;
   lt.rows = std::min(p.N_max, tn::lds_rows_cap(p));
-  lt.skip_le = 64;
+  lt.skip_le = 207;  // the 208-row file holds prog_rows + 1 (its zero row) <= 208
   return tn::launch_forward(p, t, obs, stride, B, out, lt, tn::FwdWork(), stream);
 }
 
@@ -191,7 +198,9 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
     const int K = tile->obs_per_lane, W = tile->waves_per_genome, R = tile->rows;
     if (W < 0 || W > 8 || R < 0) return TN_EINVAL;
     if (engine == TN_ENGINE_LDS && K != 0 && K != 1 && K != 2 && K != 4) return TN_EINVAL;
-    if (engine == TN_ENGINE_REG && ((K != 0 && K != 1) || (R != 0 && R != 32 && R != 64)))
+    if (engine == TN_ENGINE_REG &&
+        ((K != 0 && K != 1) ||
+         (R != 0 && R != 32 && R != 64 && R != 96 && R != 128 && R != 160 && R != 208)))
       return TN_EINVAL;
     if (engine != TN_ENGINE_AUTO && engine != TN_ENGINE_LDS && engine != TN_ENGINE_REG)
       return TN_EINVAL;
@@ -214,7 +223,7 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
   if (engine == TN_ENGINE_REG) {
     tn::RegTile rt;
     rt.waves = tile->waves_per_genome;
-    rt.rows = tile->rows;
+    rt.rf = tile->rows == 0 ? 64 : tile->rows;
     return tn::launch_forward_reg(*pop, *tr, obs, obs_genome_stride, B, out, rt, tn::FwdWork(),
                                   stream);
   }

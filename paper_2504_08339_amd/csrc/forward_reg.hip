@@ -56,6 +56,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 template <int NB, bool kLoss>
 __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
                                           const int2* __restrict__ pe,
+                                          const int32_t* __restrict__ rec, int nn, int zrow,
                                           const int32_t* __restrict__ out_pos, int orow_first,
                                           int n, int I, int O, int nbat,
                                           const float* __restrict__ xo, float* __restrict__ yo,
@@ -64,8 +65,8 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
   // from hoisting that out of the tile loop (which would keep both banks of
   // every variant live across it).
   f32x32 lo = 0.0f, hi = 0.0f;
-  asm volatile("" : "+v"(lo));
-  if (NB == 2) asm volatile("" : "+v"(hi));
+  if constexpr (NB < 32) asm volatile("" : "+v"(lo));
+  if constexpr (NB == 2) asm volatile("" : "+v"(hi));
   // inputs: coalesced loads of the tile's rows, transposed through LDS
   for (int c0 = 0; c0 < I; c0 += kChunk) {
     const int ch = min(kChunk, I - c0);
@@ -90,7 +91,12 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
     for (int j = 0; j < ch; ++j) vset<NB>(lo, hi, c0 + j, stg[lane * sr + j]);
     wave_sync();
   }
-  walk_program<NB>(lo, hi, pn, pe, n);
+  if constexpr (NB >= 32) {
+    rf_set(zrow, 0.0f);
+    walk_records<NB>(rec, pe, nn);
+  } else {
+    walk_program<NB>(lo, hi, pn, pe, n);
+  }
   // outputs
   float sse = 0.0f;
   for (int c0 = 0; c0 < O; c0 += kChunk) {
@@ -119,10 +125,11 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
 #define TN_REG_PARAMS                                                                        \
   PopView pop, const int32_t *__restrict__ status, const int32_t *__restrict__ prog_rows,     \
       const int32_t *__restrict__ n_valid, const int4 *__restrict__ prog_node,               \
-      const int2 *__restrict__ prog_edge, const int32_t *__restrict__ io_pos,                \
-      const float *__restrict__ obs, float *__restrict__ out,                                \
-      const float *__restrict__ target, RegArgs a
-#define TN_REG_ARGS pop, status, prog_rows, n_valid, prog_node, prog_edge, io_pos, obs, out, target, a
+      const int2 *__restrict__ prog_edge, const int32_t *__restrict__ prog_rec,              \
+      const int32_t *__restrict__ io_pos, const float *__restrict__ obs,                     \
+      float *__restrict__ out, const float *__restrict__ target, RegArgs a
+#define TN_REG_ARGS \
+  pop, status, prog_rows, n_valid, prog_node, prog_edge, prog_rec, io_pos, obs, out, target, a
 
 // Tiles t_begin, t_begin + t_step, ... < t_end of genome g by this wavefront;
 // returns its part of the squared error (kLoss). *st_out: the genome's
@@ -133,7 +140,8 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
                                             int t_step, float* stg, int* st_out) {
   const int lane = lane_id();
   const int I = pop.n_in, O = pop.n_out, nio = I + O;
-  const int rows = prog_rows[g];
+  // the register-file form also keeps a zero row (row prog_rows)
+  const int rows = prog_rows[g] + (NB >= 32 ? 1 : 0);
   if (rows <= a.rows_lo || (a.skip_above && rows > a.rows)) {
     *st_out = -2;
     return 0.0f;
@@ -145,6 +153,8 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
   const int64_t nb = pop.node_base(g), cb = pop.conn_base(g);
   const int4* pn = prog_node + nb;
   const int2* pe = prog_edge + cb;
+  const int32_t* rec = prog_rec + nb * 16;
+  const int nn = n - I, zrow = rows - 1;
   const int32_t* out_pos = io_pos + (int64_t)g * nio + I;
   const int orow_first = !st && lane < min(O, kChunk) ? prog_row(pn, out_pos[lane]) : 0;
   const bool one_bank = NB == 1 || (NB == 0 && rows <= 32);
@@ -160,11 +170,14 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
     }
     const float* xo = obs + (int64_t)g * a.obs_stride + (int64_t)b0 * I;
     const float* to = kLoss ? target + (int64_t)g * a.target_stride + (int64_t)b0 * O : nullptr;
-    if (one_bank)
-      sse += run_tile<1, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
+    if constexpr (NB >= 32)
+      sse += run_tile<NB, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
+                                 lane);
+    else if (one_bank)
+      sse += run_tile<1, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
                                 lane);
     else
-      sse += run_tile<2, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
+      sse += run_tile<2, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
                                 lane);
   }
   return sse;
@@ -241,31 +254,133 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PAR
   }
 }
 
-template <int NB, bool kLoss>
+// The explicit-register-file forms of the two kernels above (R rows at
+// v[kRfBase ..]); the compiler gets the VGPRs below kRfBase.
+template <int R, bool kLoss>
+__global__ __launch_bounds__(kWave * 8) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
+forward_rf_kernel(TN_REG_PARAMS, float* __restrict__ loss) {
+  rf_reserve<R>();
+  extern __shared__ __align__(16) float stage_all[];
+  __shared__ float part[8];
+  const int lane = lane_id();
+  const int wave = wave_id();
+  const int W = blockDim.x / kWave;
+  float* stg = stage_all + wave * kStage;
+  int entry, t_begin, t_end, t_step;
+  if (kLoss) {
+    entry = blockIdx.x;
+    t_begin = wave;
+    t_end = a.n_tiles;
+    t_step = W;
+  } else {
+    const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * W + wave;
+    if (item >= a.n_items) return;
+    entry = (int)(item / a.n_groups);
+    t_begin = (int)(item - (int64_t)entry * a.n_groups) * a.per_wave;
+    t_end = min(t_begin + a.per_wave, a.n_tiles);
+    t_step = 1;
+  }
+  const int g = a.genomes ? a.genomes[entry] : entry;
+  int st;
+  const float sse = reg_genome<R, kLoss>(TN_REG_ARGS, g, t_begin, t_end, t_step, stg, &st);
+  if (kLoss && st != -2) {
+    const float total = wave_sum(sse);
+    if (lane == 0) part[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float acc = 0.0f;
+      for (int v = 0; v < W; ++v) acc += part[v];
+      loss[g] = st ? __builtin_nanf("") : fmaf(a.scale, acc, a.offset);
+    }
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kWave * 8) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
+forward_rf_queue_kernel(TN_REG_PARAMS) {
+  rf_reserve<R>();
+  extern __shared__ __align__(16) float stage_all[];
+  __shared__ int base_sh;
+  const int wave = wave_id();
+  const int W = blockDim.x / kWave;
+  float* stg = stage_all + wave * kStage;
+  for (;;) {
+    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
+    __syncthreads();
+    const int base = __builtin_amdgcn_readfirstlane(base_sh);
+    __syncthreads();
+    if (base >= a.n_items) break;
+    for (int c = 0; c < a.per_wave; ++c) {
+      const int item = base + c * W + wave;
+      if (item >= a.n_items) break;
+      const int e = item / a.n_tiles, t = item - e * a.n_tiles;
+      int st;
+      reg_genome<R, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+    }
+  }
+}
+
+// Variants: 0 (one or two banks chosen per genome), 1 or 2 banks, or an
+// explicit register file of V rows.
+#define TN_REG_VARIANTS(X) X(0) X(1) X(2) X(32) X(64) X(96) X(128) X(160) X(208)
+
+template <int V, bool kLoss>
 int launch_grid(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                 const float* target, float* loss, const RegArgs& a, int grid, int waves,
                 hipStream_t stream) {
   if (grid == 0) return TN_OK;
   const size_t lds = sizeof(float) * (size_t)kStage * waves;
-  hipLaunchKernelGGL((forward_reg_kernel<NB, kLoss>), dim3((unsigned)grid), dim3(kWave * waves),
-                     lds, stream, make_view(p), t.status, t.prog_rows, t.n_valid,
-                     reinterpret_cast<const int4*>(t.prog_node),
-                     reinterpret_cast<const int2*>(t.prog_edge), t.io_pos, obs, out, target, a,
-                     loss);
+#define TN_REG_LAUNCH(K)                                                                    \
+  hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
+                     t.status, t.prog_rows, t.n_valid,                                        \
+                     reinterpret_cast<const int4*>(t.prog_node),                             \
+                     reinterpret_cast<const int2*>(t.prog_edge), t.prog_rec, t.io_pos, obs, out, \
+                     target, a,                                                              \
+                     loss)
+  if constexpr (V >= 32)
+    TN_REG_LAUNCH((forward_rf_kernel<V, kLoss>));
+  else
+    TN_REG_LAUNCH((forward_reg_kernel<V, kLoss>));
+#undef TN_REG_LAUNCH
   return check_launch();
 }
 
-template <int NB>
+template <int V>
+const void* queue_kernel() {
+  if constexpr (V >= 32)
+    return (const void*)forward_rf_queue_kernel<V>;
+  else
+    return (const void*)forward_reg_queue_kernel<V>;
+}
+
+template <int V>
 int launch_queue(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                  const RegArgs& a, int grid, int waves, hipStream_t stream) {
   if (grid == 0) return TN_OK;
   const size_t lds = sizeof(float) * (size_t)kStage * waves;
-  hipLaunchKernelGGL((forward_reg_queue_kernel<NB>), dim3((unsigned)grid), dim3(kWave * waves),
-                     lds, stream, make_view(p), t.status, t.prog_rows, t.n_valid,
-                     reinterpret_cast<const int4*>(t.prog_node),
-                     reinterpret_cast<const int2*>(t.prog_edge), t.io_pos, obs, out,
-                     (const float*)nullptr, a);
+#define TN_REG_LAUNCH(K)                                                                    \
+  hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
+                     t.status, t.prog_rows, t.n_valid,                                        \
+                     reinterpret_cast<const int4*>(t.prog_node),                             \
+                     reinterpret_cast<const int2*>(t.prog_edge), t.prog_rec, t.io_pos, obs,  \
+                     out,                                                                    \
+                     (const float*)nullptr, a)
+  if constexpr (V >= 32)
+    TN_REG_LAUNCH((forward_rf_queue_kernel<V>));
+  else
+    TN_REG_LAUNCH((forward_reg_queue_kernel<V>));
+#undef TN_REG_LAUNCH
   return check_launch();
+}
+
+bool valid_variant(int v) {
+  switch (v) {
+#define TN_CASE(V) case V:
+    TN_REG_VARIANTS(TN_CASE)
+#undef TN_CASE
+    return true;
+    default: return false;
+  }
 }
 
 }  // namespace
@@ -274,9 +389,11 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
                        int64_t obs_stride, int B, float* out, const RegTile& tile,
                        const FwdWork& work, hipStream_t stream) {
   const int waves = tile.waves <= 0 ? 4 : tile.waves;
-  const int rows = tile.rows <= 0 ? 64 : tile.rows;
-  if (waves > 8 || (rows != 32 && rows != 64) || tile.banks < 0 || tile.banks > 2 ||
-      (tile.banks == 1 && rows != 32))
+  const int rows = tile.rf ? tile.rf : (tile.rows <= 0 ? 64 : tile.rows);
+  const int variant = tile.rf ? tile.rf : tile.banks;
+  if (waves > 8 || !valid_variant(variant) ||
+      (!tile.rf && ((rows != 32 && rows != 64) || tile.banks < 0 || tile.banks > 2 ||
+                    (tile.banks == 1 && rows != 32))))
     return TN_EINVAL;
   const int n_list = work.genomes ? work.n_genomes : p.P;
   const int n_tiles = (B + kWave - 1) / kWave;
@@ -286,10 +403,12 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
     a.n_items = n_list * n_tiles;
     // items per wavefront per grab: about 4 grabs per resident workgroup
     a.per_wave = std::max(1, (int)((int64_t)a.n_items / (4LL * waves * std::max(1, work.grid))));
-    switch (tile.banks) {
-      case 1: return launch_queue<1>(p, t, obs, out, a, work.grid, waves, stream);
-      case 2: return launch_queue<2>(p, t, obs, out, a, work.grid, waves, stream);
-      default: return launch_queue<0>(p, t, obs, out, a, work.grid, waves, stream);
+    switch (variant) {
+#define TN_CASE(V) \
+  case V: return launch_queue<V>(p, t, obs, out, a, work.grid, waves, stream);
+      TN_REG_VARIANTS(TN_CASE)
+#undef TN_CASE
+      default: return TN_EINVAL;
     }
   }
   // enough wavefronts to fill the chip; each takes consecutive tiles of a genome
@@ -299,10 +418,13 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
   a.n_items = (int)std::min<int64_t>((int64_t)n_list * a.n_groups, 0x7fffffff);
   const int64_t grid = ((int64_t)n_list * a.n_groups + waves - 1) / waves;
   if (grid > 0x7fffffff || (int64_t)n_list * a.n_groups > 0x7fffffff) return TN_EUNSUPPORTED;
-  switch (tile.banks) {
-    case 1: return launch_grid<1, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
-    case 2: return launch_grid<2, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
-    default: return launch_grid<0, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
+  switch (variant) {
+#define TN_CASE(V)                                                                          \
+  case V:                                                                                   \
+    return launch_grid<V, false>(p, t, obs, out, nullptr, nullptr, a, (int)grid, waves, stream);
+    TN_REG_VARIANTS(TN_CASE)
+#undef TN_CASE
+    default: return TN_EINVAL;
   }
 }
 
@@ -318,17 +440,20 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
   return launch_grid<0, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
 }
 
-int reg_queue_grid(int banks, int waves) {
+int reg_queue_grid(int variant, int waves) {
   int dev = 0, cus = 0, per_cu = 0;
   const size_t lds = sizeof(float) * kStage * waves;
+  const void* k = nullptr;
+  switch (variant) {
+#define TN_CASE(V) \
+  case V: k = queue_kernel<V>(); break;
+    TN_REG_VARIANTS(TN_CASE)
+#undef TN_CASE
+    default: return 0;
+  }
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) {
-    const void* k = banks == 1   ? (const void*)forward_reg_queue_kernel<1>
-                    : banks == 2 ? (const void*)forward_reg_queue_kernel<2>
-                                 : (const void*)forward_reg_queue_kernel<0>;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWave * waves, lds);
-  }
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kWave * waves, lds);
   if (record_hip(e) != TN_OK) return 0;
   return std::max(1, per_cu) * cus;
 }

@@ -19,6 +19,8 @@ struct RegTile {
   int waves = 4;            // wavefronts per workgroup (1..8)
   int rows = 64;            // 32 or 64 value rows in registers
   int banks = 0;            // 1 or 2 register banks; 0: chosen per genome
+  int rf = 0;               // rows of an explicit register file (32, 64, 96, 128, 160,
+                            // 208) instead of banks; 0: banks
   int rows_lo = -1;         // genomes with prog_rows <= rows_lo are skipped
   bool skip_above = false;  // genomes with prog_rows > rows are skipped (else NaN)
 };
@@ -38,8 +40,9 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
                             int64_t obs_stride, int B, const float* target,
                             int64_t target_stride, float scale, float offset, float* out,
                             float* loss, int waves, bool skip_above, hipStream_t stream);
-// Resident workgroups (whole device) of the persistent register kernel.
-int reg_queue_grid(int banks, int waves);
+// Resident workgroups (whole device) of the persistent register kernel of a
+// variant (0, 1, 2 banks or register-file rows).
+int reg_queue_grid(int variant, int waves);
 
 int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
                    int64_t obs_stride, int B, float* out, const LdsTile& tile,

@@ -5,8 +5,10 @@
 // one launch per genome size wastes the chip on small launches. A plan sorts
 // the genomes once into length buckets by the on-chip rows their forward pass
 // needs (tn_transformed.prog_rows / n_rows):
-//   rows <= 32 and <= 64   register engine with one / two register banks
-//   rows <= 128, <= 256, <= the LDS capacity   level-parallel LDS engine
+//   prog_rows + 1 <= 32, 64, 96, 128, 160, 208   register engine, a register
+//                                                file of that many rows (one
+//                                                of them a zero row)
+//   larger: n_rows <= 256, <= the LDS capacity   level-parallel LDS engine
 // and orders each bucket longest first. Two ways to run it:
 //   tn_plan_forward_buckets  one plain launch per bucket, in order;
 //   tn_plan_forward          one persistent kernel per bucket (workgroups or
@@ -34,7 +36,7 @@ namespace {
 
 struct Bucket {
   int engine = TN_ENGINE_REG;
-  int rows_class = 32;  // REG: 32 or 64 rows; LDS: upper bound of n_rows
+  int rows_class = 32;  // REG: register-file rows (bound of prog_rows); LDS: bound of n_rows
   int count = 0;
   int max_rows = 0;     // LDS: largest n_rows in the bucket (the tile's rows)
   int64_t edges = 0;    // enabled edges over the bucket
@@ -42,6 +44,10 @@ struct Bucket {
   int grid = 0;         // workgroups of the persistent kernel
   int32_t* list = nullptr;  // device: genome indices, longest first
 };
+
+// Register-file sizes of the register-engine buckets (rows of the packed
+// program, tn_transformed.prog_rows).
+constexpr int kRegClasses[] = {32, 64, 96, 128, 160, 208};
 
 __global__ void zero_counters(int32_t* c, int n) {
   const int i = threadIdx.x;
@@ -76,7 +82,7 @@ int persistent_grid(const tn_plan& pl, const Bucket& b) {
   if (b.engine == TN_ENGINE_REG) {
     const int64_t items = (int64_t)b.count * ((pl.B + tn::kWave - 1) / tn::kWave);
     const int64_t need = (items + b.waves - 1) / b.waves;
-    return (int)std::min<int64_t>(tn::reg_queue_grid(b.rows_class == 32 ? 1 : 2, b.waves), need);
+    return (int)std::min<int64_t>(tn::reg_queue_grid(b.rows_class, b.waves), need);
   }
   return std::min(tn::lds_queue_grid(pl.pop, b.K, b.waves, b.max_rows), b.count);
 }
@@ -96,8 +102,7 @@ int launch_bucket(const tn_plan& pl, const Bucket& b, const float* obs, int64_t 
   if (b.engine == TN_ENGINE_REG) {
     tn::RegTile t;
     t.waves = b.waves;
-    t.rows = b.rows_class;
-    t.banks = b.rows_class == 32 ? 1 : 2;
+    t.rf = b.rows_class;
     return tn::launch_forward_reg(pl.pop, pl.tr, obs, stride, pl.B, out, t, w, s);
   }
   tn::LdsTile t;
@@ -285,15 +290,16 @@ int tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B
   // buckets
   const int cap = tn::lds_rows_cap(*pop);
   std::vector<Bucket> classes;
-  for (int r : {32, 64}) {
+  for (int r : kRegClasses) {
     Bucket b;
     b.engine = TN_ENGINE_REG;
     b.rows_class = r;
     classes.push_back(b);
   }
+  const int n_reg = (int)classes.size();
   std::vector<int> bounds;
-  for (int r : {128, 256, cap})
-    if (std::min(r, cap) > 64) bounds.push_back(std::min(r, cap));
+  for (int r : {256, cap})
+    if (std::min(r, cap) > kRegClasses[n_reg - 1]) bounds.push_back(std::min(r, cap));
   bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
   for (int r : bounds) {
     Bucket b;
@@ -307,16 +313,14 @@ int tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B
     const int64_t edges = status[g] ? 0 : row_ptr[rb + n_valid[g]];
     const int64_t cost = edges + n_valid[g];
     int c = -1;
-    if (status[g] || prog_rows[g] <= 32)
+    if (status[g]) {
       c = 0;
-    else if (prog_rows[g] <= 64)
-      c = 1;
-    else
-      for (size_t k = 2; k < classes.size(); ++k)
-        if (n_rows[g] <= classes[k].rows_class) {
-          c = (int)k;
-          break;
-        }
+    } else {
+      for (int k = 0; k < n_reg && c < 0; ++k)  // + 1: the register file's zero row
+        if (prog_rows[g] + 1 <= classes[k].rows_class) c = k;
+      for (size_t k = n_reg; k < classes.size() && c < 0; ++k)
+        if (n_rows[g] <= classes[k].rows_class) c = (int)k;
+    }
     if (c < 0) {  // more value rows than the LDS engine holds
       destroy(pl);
       return TN_EUNSUPPORTED;

@@ -63,6 +63,7 @@ struct TrView {
   int4* prog_node;
   int2* prog_edge;
   int32_t* prog_rows;
+  int32_t* prog_rec;
 };
 
 inline PopView make_view(const tn_population& p) {
@@ -84,6 +85,7 @@ inline TrView make_view(const tn_transformed& t) {
   v.prog_node = reinterpret_cast<int4*>(t.prog_node);
   v.prog_edge = reinterpret_cast<int2*>(t.prog_edge);
   v.prog_rows = t.prog_rows;
+  v.prog_rec = t.prog_rec;
   return v;
 }
 

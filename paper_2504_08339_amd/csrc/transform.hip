@@ -113,6 +113,7 @@ __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int s
     tr.pos_fn[nb + p] = 0;
     tr.pos_row[nb + p] = -1;
     tr.prog_node[nb + p] = make_int4(0, 0, 0, 0);
+    for (int j = 0; j < 4; ++j) reinterpret_cast<int4*>(tr.prog_rec)[(nb + p) * 4 + j] = make_int4(0, 0, 0, 0);
   }
   for (int64_t p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = 0;
   for (int64_t e = lane; e < crows; e += kWave) {
@@ -550,6 +551,47 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
     int2 q = make_int2(0, 0);
     if (e < n_edges) q = make_int2(seq[csr_src[e]], __float_as_int(pop.conn_w[cb + csr_row[e]]));
     tr.prog_edge[cb + e] = q;
+  }
+  // 11. the same program as one 16-word record per non-input position (in
+  // order; inputs are staged separately): word 0 = act | agg << 3 | row << 6 |
+  // in-edge count << 17, word 1 bias, word 2 response, word 3 the in-edge
+  // list index of the node's 7th in-edge (for nodes with more than 6), words
+  // 4..15 its first 6 in-edges as (source row, weight); unused slots read the
+  // zero row (row prog_rows, which the kernel clears) with weight +0.
+  {
+    const int zrow = pop.n_in + n_new;
+    int in_before = 0;
+    for (int base = 0; base < n_valid; base += kWave) {
+      const int p = base + lane;
+      const bool inp = p < n_valid && nkey[order_l[p]] < pop.n_in;
+      const uint64_t m = __ballot(inp);
+      if (p < n_valid && !inp) {
+        const int s = order_l[p];
+        const int r = p - (in_before + mbcnt(m));
+        const int e0 = ptr[p], ne = ptr[p + 1] - e0;
+        int32_t w[16];
+        w[0] = (int32_t)((uint32_t)pop.node_act[nb + s] | ((uint32_t)pop.node_agg[nb + s] << 3) |
+                         ((uint32_t)seq[p] << 6) | ((uint32_t)ne << 17));
+        w[1] = __float_as_int(pop.node_bias[nb + s]);
+        w[2] = __float_as_int(pop.node_resp[nb + s]);
+        w[3] = e0 + 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const bool real = i < ne;
+          w[4 + 2 * i] = real ? seq[csr_src[e0 + i]] : zrow;
+          w[5 + 2 * i] = real ? __float_as_int(pop.conn_w[cb + csr_row[e0 + i]]) : 0;
+        }
+        int4* rec = reinterpret_cast<int4*>(tr.prog_rec) + (nb + r) * 4;
+        rec[0] = make_int4(w[0], w[1], w[2], w[3]);
+        rec[1] = make_int4(w[4], w[5], w[6], w[7]);
+        rec[2] = make_int4(w[8], w[9], w[10], w[11]);
+        rec[3] = make_int4(w[12], w[13], w[14], w[15]);
+      }
+      in_before += __popcll(m);
+    }
+    const int n_nodes = n_valid - in_before;
+    for (int i = n_nodes * 4 + lane; i < nrows * 4; i += kWave)
+      reinterpret_cast<int4*>(tr.prog_rec)[nb * 4 + i] = make_int4(0, 0, 0, 0);
   }
   if (lane == 0) {
     tr.status[g] = 0;

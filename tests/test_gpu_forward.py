@@ -205,21 +205,22 @@ def test_lds_tile_shapes_and_tight_rows_bitwise(K, W):
     assert np.array_equal(short[need <= rows - 1].view(np.uint32), ref[need <= rows - 1].view(np.uint32))
 
 
-@pytest.mark.parametrize("W,rows", [(1, 64), (4, 64), (8, 64), (4, 32), (2, 32)])
+@pytest.mark.parametrize("W,rows", [(1, 64), (4, 64), (8, 64), (4, 32), (2, 32), (4, 96), (2, 208)])
 def test_register_engine_bitwise_and_row_limit(W, rows):
     """The register engine gives the LDS engine's bits for every genome whose
     packed program fits its rows and NaN for the others; observations in one
     shared batch and per genome, with a ragged last tile."""
     import paper_2504_08339_amd as tn
-    pop = synth.control_population(P=90)
-    for obs in (synth.normal_obs(90, 333, 17, 8), synth.normal_obs(1, 333, 17, 9)[0]):
+    pop = synth.control_population(P=90) if rows <= 64 else synth.batching_population(P=90)
+    I = pop.n_in
+    for obs in (synth.normal_obs(90, 333, I, 8), synth.normal_obs(1, 333, I, 9)[0]):
         dp = to_device(pop)
         tr = tn.transform(dp)
         xt = tensor(obs)
         ref = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_LDS, obs_per_lane=1,
                               waves_per_genome=4))
         y = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_REG, waves_per_genome=W, rows=rows))
-        need = host(tr.prog_rows)[:pop.P]
+        need = host(tr.prog_rows)[:pop.P] + 1      # the register file's zero row
         assert (need <= rows).any()
         fit = need <= rows
         assert np.array_equal(y[fit].view(np.uint32), ref[fit].view(np.uint32))

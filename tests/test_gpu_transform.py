@@ -19,7 +19,7 @@ def run_transform(pop):
     return {k: host(getattr(tr, k)) for k in (
         "status", "n_valid", "order", "level", "row_ptr", "edge_src", "edge_row", "edge_w",
         "pos_bias", "pos_resp", "pos_fn", "io_pos", "pos_row", "n_rows", "prog_node",
-        "prog_edge", "prog_rows")}
+        "prog_edge", "prog_rows", "prog_rec")}
 
 
 def blocks(pop, g):
@@ -245,6 +245,29 @@ def _check_prog(pop, got, g):
         assert holder[int(prow[p])] == p
     assert int(got["prog_rows"][g]) == live_max
     assert prow.max(initial=0) < live_max
+    # the same program as 16-word records of the non-input positions
+    rec = got["prog_rec"].reshape(-1, 16)[ns]
+    nr = pop.node_rows(g)
+    order = got["order"][ns][:n]
+    zrow = int(got["prog_rows"][g])
+    r = 0
+    for p in range(n):
+        if inp[p]:
+            continue
+        w = rec[r]
+        e0, ne = int(rp[p]), int(rp[p + 1] - rp[p])
+        act, agg = int(nr["act"][order[p]]), int(nr["agg"][order[p]])
+        assert w[0] == act | (agg << 3) | (int(prow[p]) << 6) | (ne << 17), (g, p)
+        assert w[1] == got["pos_bias"][ns][p:p + 1].view(np.int32)[0]
+        assert w[2] == got["pos_resp"][ns][p:p + 1].view(np.int32)[0]
+        assert w[3] == e0 + 6
+        for i in range(6):
+            if i < ne:
+                assert (w[4 + 2 * i], w[5 + 2 * i]) == (pe[e0 + i, 0], pe[e0 + i, 1])
+            else:
+                assert (w[4 + 2 * i], w[5 + 2 * i]) == (zrow, 0)
+        r += 1
+    assert np.all(rec[r:] == 0)
 
 
 @pytest.mark.parametrize("name", ["control", "batching", "cppn"])
