@@ -147,7 +147,7 @@ def batching(torch, tn, synth, args):
     # 8 B per edge; LDS engine: row_ptr, level, fn, bias, resp, row 24 B per
     # position + 8 B per edge), plus the io positions
     prog_rows = tr.prog_rows.cpu().numpy()[:pop.P]
-    reg = prog_rows + 1 <= 208
+    reg = prog_rows <= 200
     per_genome = (4 * B * (I + O) + np.where(reg, 16 * nv, 24 * nv + 4) + 8 * ne
                   + 4 * (I + O) + 12)
     total_bytes = int(per_genome.sum())
@@ -170,7 +170,7 @@ def batching(torch, tn, synth, args):
     dom = int(np.argmax(bucket_ms))
     achieved = bucket_bytes[dom] / (bucket_ms[dom] * 1e-3) / 1e9
     eng = {1: "lds", 2: "register"}
-    kern = ("forward_reg_queue_kernel" if buckets[dom]["engine"] == 2
+    kern = ("forward_rf_queue_kernel" if buckets[dom]["engine"] == 2
             else "forward_queue_kernel")
     traffic = recorded_traffic(eng[buckets[dom]["engine"]], buckets[dom]["obs_per_lane"],
                                buckets[dom]["rows_class"])
@@ -226,9 +226,8 @@ def recorded_traffic(engine, obs_per_lane, rows_class):
 
 def bucket_members(pop, tr, buckets):
     """Genome indices of each bucket, by the plan's documented rule: register
-    buckets by prog_rows + 1 (the register file's zero row; flagged genomes in
-    the first), LDS buckets by n_rows for the programs too large for the
-    largest register file."""
+    buckets by prog_rows (flagged genomes in the first), LDS buckets by n_rows
+    for the programs too large for the largest register file."""
     import numpy as np
     st = tr.status.cpu().numpy()[:pop.P]
     pr = tr.prog_rows.cpu().numpy()[:pop.P]
@@ -237,12 +236,12 @@ def bucket_members(pop, tr, buckets):
     lists, lo_reg, lo_lds = [], 0, None
     for b in buckets:
         if b["engine"] == 2:
-            m = (st == 0) & (pr + 1 > lo_reg) & (pr + 1 <= b["rows_class"])
+            m = (st == 0) & (pr > lo_reg) & (pr <= b["rows_class"])
             if lo_reg == 0:
                 m |= st != 0
             lo_reg = b["rows_class"]
         else:
-            m = (st == 0) & (pr + 1 > reg_max) & (nr <= b["rows_class"])
+            m = (st == 0) & (pr > reg_max) & (nr <= b["rows_class"])
             if lo_lds is not None:
                 m &= nr > lo_lds
             lo_lds = b["rows_class"]

@@ -201,8 +201,7 @@ int tn_validate_population(const tn_population* pop);
  *                        response bits; word 3 = index (in the conn block of
  *                        prog_edge) of the node's 7th in-edge; words 4..15 its
  *                        first 6 in-edges as {source prog row, weight bits},
- *                        unused slots {prog_rows, +0} (a row the engine keeps
- *                        at +0, so they add nothing)
+ *                        unused slots {prog_rows, +0}
  */
 typedef struct tn_transformed {
     int32_t* status;
@@ -272,18 +271,22 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr,
  *                  `rows` value rows of the tile in LDS (0: N_max), splitting
  *                  each level of the topological order among its wavefronts;
  *                  genomes whose n_rows exceeds `rows` get NaN outputs.
- *   TN_ENGINE_REG  each wavefront evaluates one genome on a tile of 64
+ *   TN_ENGINE_REG  each wavefront evaluates one genome on tiles of 64
  *                  observations (obs_per_lane 0 or 1) walking the packed
  *                  program, with the values in a register file of `rows`
- *                  rows (32, 64, 96, 128, 160 or 208; 0: 64); waves_per_genome
- *                  (1..8) wavefronts share a workgroup; genomes whose
- *                  prog_rows + 1 (the program's rows and a zero row)
- *                  exceeds `rows` get NaN outputs.
+ *                  rows per tile: 32, 64, 96, 128, 160 or 200 (one tile per
+ *                  wavefront), 100 (two consecutive tiles) or 50 (four); 0:
+ *                  64. waves_per_genome (1..8) wavefronts share a workgroup;
+ *                  genomes whose prog_rows exceeds `rows` get NaN outputs.
  *   TN_ENGINE_AUTO the library's choice for every genome (the other fields
- *                  are ignored): TN_ENGINE_REG for prog_rows < 208 (rows 64,
- *                  then 208), TN_ENGINE_LDS with rows = min(N_max, the LDS
- *                  capacity, about 600 rows on MI355X) for the rest; a genome
- *                  needing more than that capacity gets NaN outputs.
+ *                  are ignored): TN_ENGINE_REG for prog_rows <= 200 (rows
+ *                  50, 100, 128, 160, 200 when B spans at least 4 tiles of
+ *                  64; 100, 128, 160, 200 for 2 or 3 tiles; 32, 64, 96, 128,
+ *                  160, 200 for one; each launch takes the genomes the
+ *                  smaller files could not), TN_ENGINE_LDS with rows =
+ *                  min(N_max, the LDS capacity, about 600 rows on MI355X) for
+ *                  the rest; a genome needing more than that capacity gets
+ *                  NaN outputs.
  * Outputs are bitwise identical across engines and tile shapes. */
 enum tn_engine { TN_ENGINE_AUTO = 0, TN_ENGINE_LDS = 1, TN_ENGINE_REG = 2 };
 
@@ -321,11 +324,11 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
  * (the space-time trade-off of the padded encoding, Section 3.3; the
  * population-level parallelism of Sections 4.1 and 5.4). A plan sorts the genomes once
  * into length buckets by the value rows their forward pass needs:
- *   prog_rows + 1 <= 32, 64, 96, 128, 160, 208   TN_ENGINE_REG with a
- *                                             register file of that many
- *                                             rows (one of them a zero row);
+ *   prog_rows <= each register-file size TN_ENGINE_AUTO uses for B (50,
+ *                 100, 128, 160, 200 for B > 192)   TN_ENGINE_REG with that
+ *                                                   file;
  *   larger, n_rows <= 256, <= the LDS capacity (about 600 rows on MI355X)
- *                                             TN_ENGINE_LDS.
+ *                                                   TN_ENGINE_LDS.
  * Flagged genomes join the first bucket (NaN outputs). Each bucket lists its
  * genomes longest first (enabled edges + nodes).
  *
@@ -357,7 +360,7 @@ typedef struct tn_plan tn_plan;
 
 typedef struct tn_bucket_info {
     int32_t engine;       /* TN_ENGINE_REG or TN_ENGINE_LDS */
-    int32_t rows_class;   /* REG: register-file rows (bound of prog_rows + 1); LDS: bound of n_rows */
+    int32_t rows_class;   /* REG: register-file rows per tile (bound of prog_rows); LDS: bound of n_rows */
     int32_t count;        /* genomes */
     int64_t edges;        /* enabled edges over the bucket */
     tn_tile tile;         /* current tile (rows: register rows / LDS rows) */

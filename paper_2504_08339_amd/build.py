@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -45,13 +46,60 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
+def _rf_base() -> int:
+    with open(os.path.join(CSRC, "fwd_reg.hpp")) as f:
+        m = re.search(r"#define TN_RF_BASE (\d+)", f.read())
+    if not m:
+        raise RuntimeError("TN_RF_BASE not found in fwd_reg.hpp")
+    return int(m.group(1))
+
+
+def check_register_file(src: str, extra=()) -> None:
+    """The register engine keeps node values in VGPRs from TN_RF_BASE up, which
+    only its inline assembly addresses (through the index window); the
+    compiler must never place a value there. Compiles `src` to AMDGPU assembly
+    and fails if any instruction outside the inline-assembly blocks of a
+    register-file kernel names such a VGPR (an SGPR spill lane, a temporary)."""
+    base = _rf_base()
+    asm = os.path.join(BUILD, os.path.basename(src) + ".s")
+    cmd = [hipcc(), *COMMON, *extra, "--cuda-device-only", "-S", src, "-o", asm]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed on {src}:\n{res.stdout}\n{res.stderr}")
+    with open(asm) as f:
+        text = f.read()
+    heads = [(m.start(), m.group(1)) for m in re.finditer(r"^(_Z\S+):\s", text, re.M)]
+    checked = 0
+    for i, (pos, name) in enumerate(heads):
+        if "forward_rf" not in name:
+            continue
+        checked += 1
+        end = heads[i + 1][0] if i + 1 < len(heads) else len(text)
+        body = re.sub(r";;#ASMSTART.*?;;#ASMEND", "", text[pos:end], flags=re.S)
+        for line in body.split("\n"):
+            code = line.split(";")[0].strip()
+            if not code or code.startswith("."):
+                continue
+            for m in re.finditer(r"\bv\[?(\d+)(?::(\d+))?\]?", code):
+                hi = int(m.group(2) or m.group(1))
+                if hi >= base:
+                    raise RuntimeError(
+                        f"{os.path.basename(src)}: compiler-generated code of {name} uses "
+                        f"v{hi} (register file starts at v{base}): {code}")
+    if checked == 0:
+        raise RuntimeError(f"{os.path.basename(src)}: no register-file kernel found to check")
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile every csrc/*.hip and link libtnhip.so; returns its path."""
+    """Compile every csrc/*.hip, check the register engine's register file,
+    and link libtnhip.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    jobs = min(len(srcs) + 1, max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
+        rf_check = ex.submit(check_register_file, os.path.join(CSRC, "forward_reg.hip"), list(extra))
         objs = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
+        rf_check.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

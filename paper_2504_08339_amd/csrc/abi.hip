@@ -158,24 +158,27 @@ int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t
 namespace {
 
 // TN_ENGINE_AUTO: the register engine for every genome whose packed program
-// (plus the engine's zero row) fits in 208 rows (a 64-row register file, then
-// a 208-row one for the larger programs), the level-parallel LDS engine for
-// the rest (prog_rows <= N_max, so small populations need fewer launches).
+// fits in a 200-row register file, one launch per register-file size of
+// tn::reg_classes (smallest first, each skipping what an earlier one took),
+// and the level-parallel LDS engine for the rest (prog_rows <= N_max, so small
+// populations need fewer launches).
 int forward_auto(const tn_population& p, const tn_transformed& t, const float* obs,
                  int64_t stride, int B, float* out, hipStream_t stream) {
-  tn::RegTile rt;
-  rt.rf = 64;
-  rt.skip_above = p.N_max > 64;
-  int rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
-  if (rc != TN_OK || p.N_max <= 64) return rc;
-  rt.rf = 208;
-  rt.rows_lo = 64;
-  rt.skip_above = p.N_max > 208;
-  rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
-  if (rc != TN_OK || p.N_max <= 208) return rc;
+  int cls[6];
+  const int n = tn::reg_classes(B, cls);
+  int lo = -1;
+  for (int i = 0; i < n; ++i) {
+    tn::RegTile rt;
+    rt.rf = cls[i];
+    rt.rows_lo = lo;
+    rt.skip_above = p.N_max > cls[i];
+    const int rc = tn::launch_forward_reg(p, t, obs, stride, B, out, rt, tn::FwdWork(), stream);
+    if (rc != TN_OK || p.N_max <= cls[i]) return rc;
+    lo = cls[i];
+  }
   tn::LdsTile lt;
   lt.rows = std::min(p.N_max, tn::lds_rows_cap(p));
-  lt.skip_le = 207;  // the 208-row file holds prog_rows + 1 (its zero row) <= 208
+  lt.skip_le = tn::kRegRowsMax;
   return tn::launch_forward(p, t, obs, stride, B, out, lt, tn::FwdWork(), stream);
 }
 
@@ -200,7 +203,8 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
     if (engine == TN_ENGINE_LDS && K != 0 && K != 1 && K != 2 && K != 4) return TN_EINVAL;
     if (engine == TN_ENGINE_REG &&
         ((K != 0 && K != 1) ||
-         (R != 0 && R != 32 && R != 64 && R != 96 && R != 128 && R != 160 && R != 208)))
+         (R != 0 && R != 32 && R != 50 && R != 64 && R != 96 && R != 100 && R != 128 &&
+          R != 160 && R != 200)))
       return TN_EINVAL;
     if (engine != TN_ENGINE_AUTO && engine != TN_ENGINE_LDS && engine != TN_ENGINE_REG)
       return TN_EINVAL;

@@ -26,7 +26,7 @@ struct RegArgs {
   int B;
   int64_t target_stride;
   float scale, offset;
-  int n_tiles;     // tiles of 64 observations per genome
+  int n_tiles;     // units per genome: runs of rf_tiles(variant) tiles of 64 observations
   int n_groups;    // tile chunks per list entry (grid form without loss)
   int per_wave;    // grid form: tiles per chunk; persistent: items per wavefront per grab
   int rows;        // value rows in registers: 32 or 64
@@ -41,7 +41,9 @@ struct RegArgs {
 // components per observation; a row of the chunk has an odd stride, so the
 // per-lane row accesses are free of bank conflicts.
 constexpr int kChunk = 8;
-constexpr int kStage = kWave * (kChunk + 1);  // floats per wavefront
+constexpr int kStage = kWave * (kChunk + 1);  // floats per tile
+// staging regions per wavefront of variant V
+constexpr int stage_tiles(int V) { return V >= 32 ? rf_tiles(V) : 1; }
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   constexpr int kXcd = 8;
@@ -56,7 +58,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 template <int NB, bool kLoss>
 __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
                                           const int2* __restrict__ pe,
-                                          const int32_t* __restrict__ rec, int nn, int zrow,
                                           const int32_t* __restrict__ out_pos, int orow_first,
                                           int n, int I, int O, int nbat,
                                           const float* __restrict__ xo, float* __restrict__ yo,
@@ -91,12 +92,7 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
     for (int j = 0; j < ch; ++j) vset<NB>(lo, hi, c0 + j, stg[lane * sr + j]);
     wave_sync();
   }
-  if constexpr (NB >= 32) {
-    rf_set(zrow, 0.0f);
-    walk_records<NB>(rec, pe, nn);
-  } else {
-    walk_program<NB>(lo, hi, pn, pe, n);
-  }
+  walk_program<NB>(lo, hi, pn, pe, n);
   // outputs
   float sse = 0.0f;
   for (int c0 = 0; c0 < O; c0 += kChunk) {
@@ -122,6 +118,90 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
   return sse;
 }
 
+// One unit of the register-file engine: rf_tiles(R) consecutive tiles of 64
+// observations (obs b0 ...), tile k in register file k. Inputs arrive through
+// the staging buffer (one region of kStage floats per tile) and are written
+// to all tiles under one window per input; outputs leave the same way.
+template <int R, bool kLoss>
+__device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
+                                          const int2* __restrict__ pe, int nn,
+                                          const int4* __restrict__ pn,
+                                          const int32_t* __restrict__ out_pos, int orow_first,
+                                          int I, int O, int b0, int B,
+                                          const float* __restrict__ xg, float* __restrict__ yg,
+                                          const float* __restrict__ tg, float* stg, int lane) {
+  constexpr int K = rf_tiles(R);
+  int nbat[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nbat[k] = max(0, min(kWave, B - b0 - k * kWave));
+  for (int c0 = 0; c0 < I; c0 += kChunk) {
+    const int ch = min(kChunk, I - c0);
+    const int sr = ch | 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int tot = nbat[k] * ch;
+      const float* xo = xg + (int64_t)(b0 + k * kWave) * I;
+      float* sk = stg + k * kStage;
+      DivWalk dw(lane, ch, kWave);
+      for (int i0 = 0; i0 < tot; i0 += 8 * kWave) {
+        float t[8];
+        int o[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = i0 + u * kWave + lane < tot;
+          o[u] = ok ? dw.b * sr + dw.c : -1;
+          t[u] = ok ? xo[(int64_t)dw.b * I + c0 + dw.c] : 0.0f;
+          dw.step();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (o[u] >= 0) sk[o[u]] = t[u];
+      }
+    }
+    wave_sync();
+    for (int j = 0; j < ch; ++j) {
+      float x[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) x[k] = stg[k * kStage + lane * sr + j];
+      rfk_set<R>(c0 + j, x);
+    }
+    wave_sync();
+  }
+  walk_records<R>(rec, pe, nn, lane);
+  float sse = 0.0f;
+  for (int c0 = 0; c0 < O; c0 += kChunk) {
+    const int ch = min(kChunk, O - c0);
+    const int sr = ch | 1;
+    const int orow = c0 == 0 ? orow_first : (lane < ch ? prog_row(pn, out_pos[c0 + lane]) : 0);
+    for (int j = 0; j < ch; ++j) {
+      float x[K];
+      rfk_get<R>(__builtin_amdgcn_readlane(orow, j), x);
+#pragma unroll
+      for (int k = 0; k < K; ++k) stg[k * kStage + lane * sr + j] = x[k];
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int tot = nbat[k] * ch;
+      const float* sk = stg + k * kStage;
+      const int64_t ob = (int64_t)(b0 + k * kWave) * O;
+      DivWalk dw(lane, ch, kWave);
+      for (int i = lane; i < tot; i += kWave) {
+        const float y = sk[dw.b * sr + dw.c];
+        const int64_t at = ob + (int64_t)dw.b * O + c0 + dw.c;
+        if (yg) yg[at] = y;
+        if (kLoss) {
+          const float d = y - tg[at];
+          sse = fmaf(d, d, sse);
+        }
+        dw.step();
+      }
+    }
+    wave_sync();
+  }
+  return sse;
+}
+
 #define TN_REG_PARAMS                                                                        \
   PopView pop, const int32_t *__restrict__ status, const int32_t *__restrict__ prog_rows,     \
       const int32_t *__restrict__ n_valid, const int4 *__restrict__ prog_node,               \
@@ -140,8 +220,7 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
                                             int t_step, float* stg, int* st_out) {
   const int lane = lane_id();
   const int I = pop.n_in, O = pop.n_out, nio = I + O;
-  // the register-file form also keeps a zero row (row prog_rows)
-  const int rows = prog_rows[g] + (NB >= 32 ? 1 : 0);
+  const int rows = prog_rows[g];
   if (rows <= a.rows_lo || (a.skip_above && rows > a.rows)) {
     *st_out = -2;
     return 0.0f;
@@ -150,35 +229,39 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
   const int st = status[g] ? status[g] : (rows > a.rows ? -1 : 0);
   *st_out = st;
   const int n = n_valid[g];
-  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g);
+  const int64_t nb = uniform64(pop.node_base(g)), cb = uniform64(pop.conn_base(g));
   const int4* pn = prog_node + nb;
   const int2* pe = prog_edge + cb;
   const int32_t* rec = prog_rec + nb * 16;
-  const int nn = n - I, zrow = rows - 1;
+  const int nn = n - I;
   const int32_t* out_pos = io_pos + (int64_t)g * nio + I;
   const int orow_first = !st && lane < min(O, kChunk) ? prog_row(pn, out_pos[lane]) : 0;
   const bool one_bank = NB == 1 || (NB == 0 && rows <= 32);
+  constexpr int K = NB >= 32 ? rf_tiles(NB) : 1;
   float sse = 0.0f;
   for (int t = t_begin; t < t_end; t += t_step) {
-    const int b0 = t * kWave;
-    const int nbat = min(kWave, a.B - b0);
-    float* yo = out ? out + ((int64_t)g * a.B + b0) * O : nullptr;
+    const int b0 = t * K * kWave;
+    const int nobs = min(K * kWave, a.B - b0);
+    float* yg = out ? out + (int64_t)g * a.B * O : nullptr;
     if (st) {
-      if (yo)
-        for (int i = lane; i < nbat * O; i += kWave) yo[i] = __builtin_nanf("");
+      if (yg)
+        for (int i = lane; i < nobs * O; i += kWave) yg[(int64_t)b0 * O + i] = __builtin_nanf("");
       continue;
     }
-    const float* xo = obs + (int64_t)g * a.obs_stride + (int64_t)b0 * I;
-    const float* to = kLoss ? target + (int64_t)g * a.target_stride + (int64_t)b0 * O : nullptr;
-    if constexpr (NB >= 32)
-      sse += run_tile<NB, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
-                                 lane);
-    else if (one_bank)
-      sse += run_tile<1, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
-                                lane);
-    else
-      sse += run_tile<2, kLoss>(pn, pe, rec, nn, zrow, out_pos, orow_first, n, I, O, nbat, xo, yo, to, stg,
-                                lane);
+    const float* xg = obs + (int64_t)g * a.obs_stride;
+    const float* tg = kLoss ? target + (int64_t)g * a.target_stride : nullptr;
+    if constexpr (NB >= 32) {
+      sse += run_unit<NB, kLoss>(rec, pe, nn, pn, out_pos, orow_first, I, O, b0, a.B, xg, yg,
+                                 tg, stg, lane);
+    } else {
+      const float* xo = xg + (int64_t)b0 * I;
+      float* yo = yg ? yg + (int64_t)b0 * O : nullptr;
+      const float* to = kLoss ? tg + (int64_t)b0 * O : nullptr;
+      if (one_bank)
+        sse += run_tile<1, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nobs, xo, yo, to, stg, lane);
+      else
+        sse += run_tile<2, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nobs, xo, yo, to, stg, lane);
+    }
   }
   return sse;
 }
@@ -265,7 +348,7 @@ forward_rf_kernel(TN_REG_PARAMS, float* __restrict__ loss) {
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage;
+  float* stg = stage_all + wave * kStage * rf_tiles(R);
   int entry, t_begin, t_end, t_step;
   if (kLoss) {
     entry = blockIdx.x;
@@ -303,7 +386,7 @@ forward_rf_queue_kernel(TN_REG_PARAMS) {
   __shared__ int base_sh;
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage;
+  float* stg = stage_all + wave * kStage * rf_tiles(R);
   for (;;) {
     if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
     __syncthreads();
@@ -321,15 +404,16 @@ forward_rf_queue_kernel(TN_REG_PARAMS) {
 }
 
 // Variants: 0 (one or two banks chosen per genome), 1 or 2 banks, or an
-// explicit register file of V rows.
-#define TN_REG_VARIANTS(X) X(0) X(1) X(2) X(32) X(64) X(96) X(128) X(160) X(208)
+// explicit register file of V rows per tile (50: four tiles per wavefront,
+// 100: two, the others one).
+#define TN_REG_VARIANTS(X) X(0) X(1) X(2) X(32) X(50) X(64) X(96) X(100) X(128) X(160) X(200)
 
 template <int V, bool kLoss>
 int launch_grid(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                 const float* target, float* loss, const RegArgs& a, int grid, int waves,
                 hipStream_t stream) {
   if (grid == 0) return TN_OK;
-  const size_t lds = sizeof(float) * (size_t)kStage * waves;
+  const size_t lds = sizeof(float) * (size_t)kStage * stage_tiles(V) * waves;
 #define TN_REG_LAUNCH(K)                                                                    \
   hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
                      t.status, t.prog_rows, t.n_valid,                                        \
@@ -357,7 +441,7 @@ template <int V>
 int launch_queue(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                  const RegArgs& a, int grid, int waves, hipStream_t stream) {
   if (grid == 0) return TN_OK;
-  const size_t lds = sizeof(float) * (size_t)kStage * waves;
+  const size_t lds = sizeof(float) * (size_t)kStage * stage_tiles(V) * waves;
 #define TN_REG_LAUNCH(K)                                                                    \
   hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
                      t.status, t.prog_rows, t.n_valid,                                        \
@@ -396,7 +480,9 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
                     (tile.banks == 1 && rows != 32))))
     return TN_EINVAL;
   const int n_list = work.genomes ? work.n_genomes : p.P;
-  const int n_tiles = (B + kWave - 1) / kWave;
+  // units of stage_tiles(variant) tiles of 64 observations per genome
+  const int kt = stage_tiles(variant);
+  const int n_tiles = ((B + kWave - 1) / kWave + kt - 1) / kt;
   RegArgs a{obs_stride, B,  0, 0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.rows_lo,
             tile.skip_above ? 1 : 0, work.genomes, work.queue, 0};
   if (work.queue) {
@@ -442,7 +528,7 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
 
 int reg_queue_grid(int variant, int waves) {
   int dev = 0, cus = 0, per_cu = 0;
-  const size_t lds = sizeof(float) * kStage * waves;
+  const size_t lds = sizeof(float) * kStage * stage_tiles(variant) * waves;
   const void* k = nullptr;
   switch (variant) {
 #define TN_CASE(V) \

@@ -19,8 +19,9 @@ struct RegTile {
   int waves = 4;            // wavefronts per workgroup (1..8)
   int rows = 64;            // 32 or 64 value rows in registers
   int banks = 0;            // 1 or 2 register banks; 0: chosen per genome
-  int rf = 0;               // rows of an explicit register file (32, 64, 96, 128, 160,
-                            // 208) instead of banks; 0: banks
+  int rf = 0;               // rows per tile of an explicit register file instead of
+                            // banks (32, 64, 96, 128, 160, 200: one tile of 64
+                            // observations per wavefront; 100: two; 50: four); 0: banks
   int rows_lo = -1;         // genomes with prog_rows <= rows_lo are skipped
   bool skip_above = false;  // genomes with prog_rows > rows are skipped (else NaN)
 };
@@ -32,6 +33,23 @@ struct LdsTile {
   int rows = 0;       // value rows per tile (0: N_max)
   int skip_le = -1;   // genomes with prog_rows <= skip_le are skipped
 };
+
+// Register-file sizes (rows per tile) the automatic engine choice and plans
+// use for B observations per genome, smallest first: files that hold several
+// tiles per wavefront when B spans that many tiles.
+inline int reg_classes(int B, int (&cls)[6]) {
+  const int tiles = (B + 63) / 64;
+  int n = 0;
+  if (tiles >= 4) {
+    for (int r : {50, 100, 128, 160, 200}) cls[n++] = r;
+  } else if (tiles >= 2) {
+    for (int r : {100, 128, 160, 200}) cls[n++] = r;
+  } else {
+    for (int r : {32, 64, 96, 128, 160, 200}) cls[n++] = r;
+  }
+  return n;
+}
+constexpr int kRegRowsMax = 200;  // largest register file (rows per tile)
 
 int launch_forward_reg(const tn_population& p, const tn_transformed& t, const float* obs,
                        int64_t obs_stride, int B, float* out, const RegTile& tile,

@@ -5,9 +5,13 @@
 // one launch per genome size wastes the chip on small launches. A plan sorts
 // the genomes once into length buckets by the on-chip rows their forward pass
 // needs (tn_transformed.prog_rows / n_rows):
-//   prog_rows + 1 <= 32, 64, 96, 128, 160, 208   register engine, a register
-//                                                file of that many rows (one
-//                                                of them a zero row)
+//   prog_rows <= 50, 100, 128, 160, 200   register engine, a register file of
+//                                         that many rows per tile (50: four
+//                                         tiles of 64 observations per
+//                                         wavefront, 100: two), for B >= 256;
+//                                         fewer tiles per wavefront (and the
+//                                         one-tile sizes 32, 64, 96) for B
+//                                         spanning fewer tiles
 //   larger: n_rows <= 256, <= the LDS capacity   level-parallel LDS engine
 // and orders each bucket longest first. Two ways to run it:
 //   tn_plan_forward_buckets  one plain launch per bucket, in order;
@@ -45,10 +49,6 @@ struct Bucket {
   int32_t* list = nullptr;  // device: genome indices, longest first
 };
 
-// Register-file sizes of the register-engine buckets (rows of the packed
-// program, tn_transformed.prog_rows).
-constexpr int kRegClasses[] = {32, 64, 96, 128, 160, 208};
-
 __global__ void zero_counters(int32_t* c, int n) {
   const int i = threadIdx.x;
   if (i < n) c[i] = 0;
@@ -80,7 +80,8 @@ using tn::record_hip;
 // Resident workgroups of the bucket's persistent kernel, capped by its work.
 int persistent_grid(const tn_plan& pl, const Bucket& b) {
   if (b.engine == TN_ENGINE_REG) {
-    const int64_t items = (int64_t)b.count * ((pl.B + tn::kWave - 1) / tn::kWave);
+    const int kt = tn::rf_tiles_of(b.rows_class);  // tiles per wavefront
+    const int64_t items = (int64_t)b.count * (((pl.B + tn::kWave - 1) / tn::kWave + kt - 1) / kt);
     const int64_t need = (items + b.waves - 1) / b.waves;
     return (int)std::min<int64_t>(tn::reg_queue_grid(b.rows_class, b.waves), need);
   }
@@ -290,16 +291,17 @@ int tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B
   // buckets
   const int cap = tn::lds_rows_cap(*pop);
   std::vector<Bucket> classes;
-  for (int r : kRegClasses) {
+  int reg_cls[6];
+  const int n_reg = tn::reg_classes(B, reg_cls);
+  for (int i = 0; i < n_reg; ++i) {
     Bucket b;
     b.engine = TN_ENGINE_REG;
-    b.rows_class = r;
+    b.rows_class = reg_cls[i];
     classes.push_back(b);
   }
-  const int n_reg = (int)classes.size();
   std::vector<int> bounds;
   for (int r : {256, cap})
-    if (std::min(r, cap) > kRegClasses[n_reg - 1]) bounds.push_back(std::min(r, cap));
+    if (std::min(r, cap) > tn::kRegRowsMax) bounds.push_back(std::min(r, cap));
   bounds.erase(std::unique(bounds.begin(), bounds.end()), bounds.end());
   for (int r : bounds) {
     Bucket b;
@@ -316,8 +318,8 @@ int tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B
     if (status[g]) {
       c = 0;
     } else {
-      for (int k = 0; k < n_reg && c < 0; ++k)  // + 1: the register file's zero row
-        if (prog_rows[g] + 1 <= classes[k].rows_class) c = k;
+      for (int k = 0; k < n_reg && c < 0; ++k)
+        if (prog_rows[g] <= classes[k].rows_class) c = k;
       for (size_t k = n_reg; k < classes.size() && c < 0; ++k)
         if (n_rows[g] <= classes[k].rows_class) c = (int)k;
     }

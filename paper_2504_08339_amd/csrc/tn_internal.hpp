@@ -9,6 +9,10 @@
 
 namespace tn {
 
+// Tiles of 64 observations per wavefront of the register engine's register
+// file of R rows per tile (50 rows: four, 100: two, other sizes: one).
+__host__ __device__ constexpr int rf_tiles_of(int R) { return R == 50 ? 4 : R == 100 ? 2 : 1; }
+
 constexpr int kWave = 64;
 
 // Population descriptor passed to kernels by value.
@@ -96,6 +100,15 @@ constexpr uint32_t kFnInput = 0x80000000u;
 // ------------------------------------------------------------ wave helpers
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// A 64-bit value that is the same on every lane, as a wavefront-uniform value
+// (offsets computed with 64-bit vector multiplies stay in vector registers;
+// made uniform, the addresses built from them stay on the scalar unit).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Index of this wavefront in its workgroup, as a wavefront-uniform value (the
 // compiler cannot see that threadIdx.x / 64 is uniform; anything derived from

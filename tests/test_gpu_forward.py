@@ -98,14 +98,17 @@ def test_control_full_size_sampled():
     check(pop, obs, Y, sample.tolist())
 
 
-def test_all_activations_aggregations_and_response():
+@pytest.mark.parametrize("B", [130, 300])
+def test_all_activations_aggregations_and_response(B):
+    """Every activation and aggregation with random responses; 130
+    observations run two tiles per wavefront, 300 four."""
     rng = np.random.default_rng(5)
     pop = synth.cppn_population(P=80, seed=77)
     valid = pop.node_key >= 0
     pop.node_act[valid] = rng.integers(0, 7, size=int(valid.sum()))
     pop.node_agg[valid] = rng.integers(0, 6, size=int(valid.sum()))
     pop.node_resp[valid] = rng.uniform(-2, 2, size=int(valid.sum())).astype(np.float32)
-    obs = rng.uniform(-1.5, 1.5, size=(80, 130, pop.n_in)).astype(np.float32)
+    obs = rng.uniform(-1.5, 1.5, size=(80, B, pop.n_in)).astype(np.float32)
     Y = gpu_forward(pop, obs)
     check(pop, obs, Y)
 
@@ -205,26 +208,57 @@ def test_lds_tile_shapes_and_tight_rows_bitwise(K, W):
     assert np.array_equal(short[need <= rows - 1].view(np.uint32), ref[need <= rows - 1].view(np.uint32))
 
 
-@pytest.mark.parametrize("W,rows", [(1, 64), (4, 64), (8, 64), (4, 32), (2, 32), (4, 96), (2, 208)])
+@pytest.mark.parametrize("W,rows", [(1, 64), (4, 64), (8, 64), (4, 32), (2, 32), (4, 96), (2, 200),
+                                    (1, 50), (4, 50), (8, 50), (2, 100), (4, 100)])
 def test_register_engine_bitwise_and_row_limit(W, rows):
     """The register engine gives the LDS engine's bits for every genome whose
     packed program fits its rows and NaN for the others; observations in one
-    shared batch and per genome, with a ragged last tile."""
+    shared batch and per genome, with a ragged last tile; the files of 50 and
+    100 rows (four and two tiles per wavefront) also with a last wavefront
+    whose later tiles are empty (333 observations) or that has a single
+    partial tile (40)."""
     import paper_2504_08339_amd as tn
-    pop = synth.control_population(P=90) if rows <= 64 else synth.batching_population(P=90)
+    pop = synth.control_population(P=90) if rows in (32, 64) else synth.batching_population(P=90)
     I = pop.n_in
-    for obs in (synth.normal_obs(90, 333, I, 8), synth.normal_obs(1, 333, I, 9)[0]):
+    cases = [synth.normal_obs(90, 333, I, 8), synth.normal_obs(1, 333, I, 9)[0]]
+    if rows in (50, 100):
+        cases.append(synth.normal_obs(90, 40, I, 10))
+    for obs in cases:
         dp = to_device(pop)
         tr = tn.transform(dp)
         xt = tensor(obs)
         ref = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_LDS, obs_per_lane=1,
                               waves_per_genome=4))
         y = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_REG, waves_per_genome=W, rows=rows))
-        need = host(tr.prog_rows)[:pop.P] + 1      # the register file's zero row
+        need = host(tr.prog_rows)[:pop.P]
         assert (need <= rows).any()
         fit = need <= rows
         assert np.array_equal(y[fit].view(np.uint32), ref[fit].view(np.uint32))
         assert np.isnan(y[~fit]).all()
+
+
+@pytest.mark.parametrize("rows", [50, 100])
+def test_register_file_tiles_agree_bitwise(rows):
+    """The tiles a wavefront holds in one register file (four at 50 rows, two
+    at 100) each see the same 64 observations here, so their outputs must
+    agree bit for bit, and with the LDS engine: a window reading a stale index
+    shows up as a tile that disagrees."""
+    import paper_2504_08339_amd as tn
+    pop = synth.batching_population(P=600)
+    base = synth.normal_obs(pop.P, 64, pop.n_in, 12)
+    obs = np.concatenate([base] * 8, axis=1)                  # 512 observations
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    xt = tensor(obs)
+    ref = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_LDS, obs_per_lane=1,
+                          waves_per_genome=4))
+    for W in (1, 4):
+        y = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_REG, rows=rows, waves_per_genome=W))
+        fit = host(tr.prog_rows)[:pop.P] <= rows
+        assert fit.sum() > 100
+        tiles = y[fit].reshape(int(fit.sum()), 8, 64, pop.n_out).view(np.uint32)
+        assert np.array_equal(tiles, np.broadcast_to(tiles[:, :1], tiles.shape))
+        assert np.array_equal(y[fit].view(np.uint32), ref[fit].view(np.uint32))
 
 
 @pytest.mark.parametrize("name", ["batching", "cppn", "differentiation"])

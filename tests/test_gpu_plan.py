@@ -29,10 +29,13 @@ def _setup(P, B, seed=41):
     return tn, pop, dp, tr, obs
 
 
-def test_plan_buckets_cover_population_and_match_forward():
-    tn, pop, dp, tr, obs = _setup(600, 150)
+@pytest.mark.parametrize("B", [150, 300, 50])
+def test_plan_buckets_cover_population_and_match_forward(B):
+    """Register buckets hold two tiles per wavefront (150 observations), four
+    (300, the last wavefront of a genome half empty) or one (50)."""
+    tn, pop, dp, tr, obs = _setup(600, B)
     xt = tensor(obs)
-    plan = tn.Plan(dp, tr, 150)
+    plan = tn.Plan(dp, tr, B)
     bks = plan.buckets()
     assert sum(b["count"] for b in bks) == pop.P
     engines = {b["engine"] for b in bks}
