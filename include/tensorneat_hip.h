@@ -407,7 +407,7 @@ typedef struct tn_substrate {
 } tn_substrate;
 
 /* Weights of every CPPN genome (pop->n_in must be 5, pop->n_out 1; tr from
- * tn_transform on pop; every genome's prog_rows <= 64, else its weights are
+ * tn_transform on pop; every genome's prog_rows <= 50, else its weights are
  * NaN, as are a flagged genome's). Outputs, bfloat16 bits, transposed so that
  * rows run along the source index:
  *   w1t [P][S][S]       w1t[g][t][s] = weight input s -> hidden t

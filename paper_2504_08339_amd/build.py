@@ -54,6 +54,11 @@ def _rf_base() -> int:
     return int(m.group(1))
 
 
+# kernels that keep an explicit register file (names as they appear mangled)
+RF_KERNELS = ("forward_rf", "cppn_query_kernel")
+RF_SOURCES = ("forward_reg.hip", "hyperneat.hip")
+
+
 def check_register_file(src: str, extra=()) -> None:
     """The register engine keeps node values in VGPRs from TN_RF_BASE up, which
     only its inline assembly addresses (through the index window); the
@@ -71,7 +76,7 @@ def check_register_file(src: str, extra=()) -> None:
     heads = [(m.start(), m.group(1)) for m in re.finditer(r"^(_Z\S+):\s", text, re.M)]
     checked = 0
     for i, (pos, name) in enumerate(heads):
-        if "forward_rf" not in name:
+        if not any(k in name for k in RF_KERNELS):
             continue
         checked += 1
         end = heads[i + 1][0] if i + 1 < len(heads) else len(text)
@@ -95,11 +100,13 @@ def build(verbose: bool = False, extra=()) -> str:
     and link libtnhip.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = min(len(srcs) + 1, max(1, min(8, os.cpu_count() or 1)))
+    jobs = min(len(srcs) + 2, max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        rf_check = ex.submit(check_register_file, os.path.join(CSRC, "forward_reg.hip"), list(extra))
+        rf_checks = [ex.submit(check_register_file, os.path.join(CSRC, f), list(extra))
+                     for f in RF_SOURCES]
         objs = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
-        rf_check.result()
+        for c in rf_checks:
+            c.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -46,84 +46,90 @@ __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float
 
 // ------------------------------------------------------------------ query
 
-template <int NB>
-__device__ __forceinline__ float cppn_eval(const int4* __restrict__ pn, const int2* __restrict__ pe,
-                                           int n, int out_row, float xs, float ys, float xt,
-                                           float yt) {
-  f32x32 lo = 0.0f, hi = 0.0f;
-  asm volatile("" : "+v"(lo));
-  if (NB == 2) asm volatile("" : "+v"(hi));
-  vset<NB>(lo, hi, 0, xs);
-  vset<NB>(lo, hi, 1, ys);
-  vset<NB>(lo, hi, 2, xt);
-  vset<NB>(lo, hi, 3, yt);
-  vset<NB>(lo, hi, 4, 1.0f);
-  walk_program<NB>(lo, hi, pn, pe, n);
-  return vget<NB>(lo, hi, out_row);
-}
+// Workgroups over (genome, chunk of query units); each wavefront takes
+// `per_wave` consecutive units of 4 x 64 queries and runs the CPPN's packed
+// program on them with the register engine's walk (a register file of 50 rows
+// per tile, four tiles under each index window). Queries 0 .. S*S-1 fill w1t
+// (t = q / S, s = q % S), the next S*m fill w2t (j, s); S*S is a multiple of
+// 4096, so a unit lies in one of the two.
+constexpr int kQueryRows = 50;
 
-// Workgroups over (genome, chunk of query tiles); each wavefront takes
-// `per_wave` consecutive tiles of 64 queries. Queries 0 .. S*S-1 fill w1t
-// (t = q / S, s = q % S), the next S*m fill w2t (j, s).
-__global__ __launch_bounds__(256) void cppn_query_kernel(
-    PopView pop, const int32_t* __restrict__ status, const int32_t* __restrict__ prog_rows,
-    const int32_t* __restrict__ n_valid, const int4* __restrict__ prog_node,
-    const int2* __restrict__ prog_edge, const int32_t* __restrict__ io_pos, SubGeom sg,
-    int n_chunks, int per_wave, uint16_t* __restrict__ w1t, uint16_t* __restrict__ w2t,
-    float* __restrict__ raw1, float* __restrict__ raw2) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
+cppn_query_kernel(PopView pop, const int32_t* __restrict__ status,
+                  const int32_t* __restrict__ prog_rows, const int32_t* __restrict__ n_valid,
+                  const int4* __restrict__ prog_node, const int2* __restrict__ prog_edge,
+                  const int32_t* __restrict__ prog_rec, const int32_t* __restrict__ io_pos,
+                  SubGeom sg, int n_chunks, int per_wave, uint16_t* __restrict__ w1t,
+                  uint16_t* __restrict__ w2t, float* __restrict__ raw1, float* __restrict__ raw2) {
+  constexpr int R = kQueryRows, K = rf_tiles(kQueryRows), kUnit = K * kWave;
+  rf_reserve<R>();
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
   const int g = blockIdx.x / n_chunks;
   const int chunk = blockIdx.x - g * n_chunks;
   const int Q1 = sg.S * sg.S, Q = Q1 + sg.S * sg.n_out;  // < 2^31 (checked on the host)
-  const int n_tiles = (Q + kWave - 1) / kWave;
-  const int t0 = (chunk * W + wave) * per_wave;
-  const int t1 = min(t0 + per_wave, n_tiles);
-  const int rows = prog_rows[g];
-  const bool bad = status[g] != 0 || rows > 64;
-  const int n = n_valid[g];
-  const int4* pn = prog_node + pop.node_base(g);
-  const int2* pe = prog_edge + pop.conn_base(g);
+  const int n_units = (Q + kUnit - 1) / kUnit;
+  const int u0 = (chunk * W + wave) * per_wave;
+  const int u1 = min(u0 + per_wave, n_units);
+  const bool bad = status[g] != 0 || prog_rows[g] > R;
+  const int nn = n_valid[g] - pop.n_in;
+  const int64_t nb = uniform64(pop.node_base(g)), cb = uniform64(pop.conn_base(g));
+  const int32_t* rec = prog_rec + nb * 16;
+  const int2* pe = prog_edge + cb;
   const int nio = pop.n_in + pop.n_out;
-  const int out_row = bad ? 0 : ((pn[io_pos[(int64_t)g * nio + pop.n_in]].y >> 16) & 0x7fff);
+  const int out_row =
+      bad ? 0 : ((prog_node[nb + io_pos[(int64_t)g * nio + pop.n_in]].y >> 16) & 0x7fff);
   uint16_t* W1 = w1t + (int64_t)g * Q1;
   uint16_t* W2 = w2t + (int64_t)g * sg.S * sg.n_out;
   float* R1 = raw1 ? raw1 + (int64_t)g * Q1 : nullptr;
   float* R2 = raw2 ? raw2 + (int64_t)g * sg.S * sg.n_out : nullptr;
-  for (int t = t0; t < t1; ++t) {
-    const int q = t * kWave + lane;
-    const bool live = q < Q;
-    const bool first = q < Q1;
-    const int qq = first ? q : q - Q1;
-    const int tgt = qq / sg.S;
-    const int src = qq - tgt * sg.S;
-    const int rs = src / sg.grid, cs = src - rs * sg.grid;
-    const float xs = fmaf((float)cs, sg.step, -1.0f), ys = fmaf((float)rs, sg.step, -1.0f);
-    float xt, yt;
-    if (first) {
-      const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
-      xt = fmaf((float)ct, sg.step, -1.0f);
-      yt = fmaf((float)rt, sg.step, -1.0f);
+  for (int u = u0; u < u1; ++u) {
+    const bool first = u * kUnit < Q1;
+    const int base = first ? u * kUnit : u * kUnit - Q1;
+    float y[K];
+    if (bad) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) y[k] = __builtin_nanf("");
     } else {
-      xt = sg.n_out > 1 ? fmaf((float)tgt, sg.ostep, -1.0f) : 0.0f;
-      yt = 0.0f;
+      // the CPPN's inputs (x_s, y_s, x_t, y_t, 1) at rows 0..4 of every tile
+      float xs[K], ys[K], xt[K], yt[K], one[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int qq = base + k * kWave + lane;
+        const int tgt = qq / sg.S;
+        const int src = qq - tgt * sg.S;
+        const int rs = src / sg.grid, cs = src - rs * sg.grid;
+        xs[k] = fmaf((float)cs, sg.step, -1.0f);
+        ys[k] = fmaf((float)rs, sg.step, -1.0f);
+        if (first) {
+          const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
+          xt[k] = fmaf((float)ct, sg.step, -1.0f);
+          yt[k] = fmaf((float)rt, sg.step, -1.0f);
+        } else {
+          xt[k] = sg.n_out > 1 ? fmaf((float)tgt, sg.ostep, -1.0f) : 0.0f;
+          yt[k] = 0.0f;
+        }
+        one[k] = 1.0f;
+      }
+      rfk_set<R>(0, xs);
+      rfk_set<R>(1, ys);
+      rfk_set<R>(2, xt);
+      rfk_set<R>(3, yt);
+      rfk_set<R>(4, one);
+      walk_records<R>(rec, pe, nn, lane);
+      rfk_get<R>(out_row, y);
     }
-    float y;
-    if (bad)
-      y = __builtin_nanf("");
-    else if (rows <= 32)
-      y = cppn_eval<1>(pn, pe, n, out_row, xs, ys, xt, yt);
-    else
-      y = cppn_eval<2>(pn, pe, n, out_row, xs, ys, xt, yt);
-    const uint16_t wb = bf16_bits(fabsf(y) < sg.thr ? 0.0f : y);
-    if (live) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int qq = base + k * kWave + lane;
+      const uint16_t wb = bf16_bits(fabsf(y[k]) < sg.thr ? 0.0f : y[k]);
       if (first) {
         W1[qq] = wb;
-        if (R1) R1[qq] = y;
-      } else {
+        if (R1) R1[qq] = y[k];
+      } else if (qq < sg.S * sg.n_out) {
         W2[qq] = wb;
-        if (R2) R2[qq] = y;
+        if (R2) R2[qq] = y[k];
       }
     }
   }
@@ -529,17 +535,18 @@ int launch_cppn_query(const tn_population& p, const tn_transformed& t, const tn_
   sg.step = 2.0f / (float)(sub.grid - 1);
   sg.ostep = sub.n_out > 1 ? 2.0f / (float)(sub.n_out - 1) : 0.0f;
   const int64_t Q = (int64_t)sg.S * sg.S + (int64_t)sg.S * sg.n_out;  // < 2^31 by check_substrate
-  const int64_t n_tiles = (Q + kWave - 1) / kWave;
-  const int waves = 4, per_wave = 16;
-  const int n_chunks = (int)((n_tiles + (int64_t)waves * per_wave - 1) / ((int64_t)waves * per_wave));
+  const int64_t unit = (int64_t)rf_tiles(kQueryRows) * kWave;
+  const int64_t n_units = (Q + unit - 1) / unit;
+  const int waves = 4, per_wave = 4;
+  const int n_chunks = (int)((n_units + (int64_t)waves * per_wave - 1) / ((int64_t)waves * per_wave));
   const int64_t grid = (int64_t)p.P * n_chunks;
   if (grid == 0) return TN_OK;
   if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
   hipLaunchKernelGGL(cppn_query_kernel, dim3((unsigned)grid), dim3(kWave * waves), 0, stream,
                      make_view(p), t.status, t.prog_rows, t.n_valid,
                      reinterpret_cast<const int4*>(t.prog_node),
-                     reinterpret_cast<const int2*>(t.prog_edge), t.io_pos, sg, n_chunks, per_wave,
-                     w1t, w2t, raw1, raw2);
+                     reinterpret_cast<const int2*>(t.prog_edge), t.prog_rec, t.io_pos, sg,
+                     n_chunks, per_wave, w1t, w2t, raw1, raw2);
   return check_launch();
 }
 
