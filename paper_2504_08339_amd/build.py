@@ -55,7 +55,7 @@ def _rf_base() -> int:
 
 
 # kernels that keep an explicit register file (names as they appear mangled)
-RF_KERNELS = ("forward_rf", "cppn_query_kernel")
+RF_KERNELS = ("forward_rf", "cppn_query_kernel", "cppn_backward_kernel")
 RF_SOURCES = ("forward_reg.hip", "hyperneat.hip")
 
 

@@ -324,14 +324,87 @@ __global__ __launch_bounds__(256) void transpose_x_kernel(const uint16_t* __rest
 
 // ----------------------------------------------------------- CPPN adjoint
 
-// Limits of the CPPN adjoint: node values and per-lane gradient accumulators
-// live in registers, indexed by topological position (no row reuse: the
-// reverse sweep needs every value).
+// Limits of the CPPN adjoint: node values, pre-activations and upstream
+// gradients live in registers indexed by topological position (no row reuse:
+// the reverse sweep needs every value).
 constexpr int kCppnNodes = 32, kCppnEdges = 64;
 constexpr int kCppnPart = kCppnEdges + kCppnNodes;  // partial sums per wavefront
 
-__device__ __forceinline__ float bget(const f32x32& b, int i) { return b[i]; }
-__device__ __forceinline__ void bset(f32x32& b, int i, float x) { b[i] = x; }
+// Register file of the adjoint, per tile of 64 queries: values V at rows
+// 0..31, pre-activations Z at 32..63, upstream gradients G at 64..95; two
+// tiles per wavefront, tile 0 at v56, tile 1 at v152 (v56..v247 in all, the
+// compiler keeping v0..v55). Windows wait two cycles after s_set_gpr_idx_on
+// (see fwd_reg.hpp).
+__device__ __forceinline__ void adj_reserve() { asm volatile("" ::: "v247"); }
+
+// s{0,1} += w * V[j] of tiles 0 and 1.
+__device__ __forceinline__ void adj_fma_v(float& s0, float& s1, float w, int j) {
+  asm volatile(
+      "s_set_gpr_idx_on %3, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %2, v56\n\t"
+      "v_fmac_f32 %1, %2, v152\n\ts_set_gpr_idx_off"
+      : "+v"(s0), "+v"(s1)
+      : "s"(w), "s"(j));
+}
+// V[p] := v{0,1}
+__device__ __forceinline__ void adj_set_v(int p, float v0, float v1) {
+  asm volatile(
+      "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
+      "v_mov_b32 v152, %1\n\ts_set_gpr_idx_off" ::"v"(v0),
+      "v"(v1), "s"(p));
+}
+// V[p] := v{0,1}, Z[p] := z{0,1}
+__device__ __forceinline__ void adj_set_vz(int p, float v0, float v1, float z0, float z1) {
+  asm volatile(
+      "s_set_gpr_idx_on %4, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
+      "v_mov_b32 v152, %1\n\tv_mov_b32 v88, %2\n\tv_mov_b32 v184, %3\n\ts_set_gpr_idx_off" ::"v"(v0),
+      "v"(v1), "v"(z0), "v"(z1), "s"(p));
+}
+// G[p] := g{0,1}
+__device__ __forceinline__ void adj_set_g(int p, float g0, float g1) {
+  asm volatile(
+      "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v120, %0\n\t"
+      "v_mov_b32 v216, %1\n\ts_set_gpr_idx_off" ::"v"(g0),
+      "v"(g1), "s"(p));
+}
+// t{0,1} := V[j]
+__device__ __forceinline__ void adj_get_v(int j, float& t0, float& t1) {
+  asm volatile(
+      "s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v56\n\t"
+      "v_mov_b32 %1, v152\n\ts_set_gpr_idx_off"
+      : "=v"(t0), "=v"(t1)
+      : "s"(j));
+}
+// G[p], V[p], Z[p] of both tiles
+__device__ __forceinline__ void adj_get_gvz(int p, float& g0, float& g1, float& v0, float& v1,
+                                            float& z0, float& z1) {
+  asm volatile(
+      "s_set_gpr_idx_on %6, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v120\n\t"
+      "v_mov_b32 %1, v216\n\tv_mov_b32 %2, v56\n\tv_mov_b32 %3, v152\n\t"
+      "v_mov_b32 %4, v88\n\tv_mov_b32 %5, v184\n\ts_set_gpr_idx_off"
+      : "=v"(g0), "=v"(g1), "=v"(v0), "=v"(v1), "=v"(z0), "=v"(z1)
+      : "s"(p));
+}
+// G[j] += dt{0,1} * w, one indexed read-modify-write per tile
+__device__ __forceinline__ void adj_fma_g(int j, float dt0, float dt1, float w) {
+  asm volatile(
+      "s_set_gpr_idx_on %3, gpr_idx(SRC2,DST)\n\ts_nop 1\n\tv_fma_f32 v120, %0, %2, v120\n\t"
+      "v_fma_f32 v216, %1, %2, v216\n\ts_set_gpr_idx_off" ::"v"(dt0),
+      "v"(dt1), "s"(w), "s"(j));
+}
+// G := 0 for both tiles (fixed registers, no window)
+__device__ __forceinline__ void adj_zero_g() {
+  asm volatile(
+#define TN_Z4(a, b, c, d) "v_mov_b32 v" #a ", 0\n\tv_mov_b32 v" #b ", 0\n\tv_mov_b32 v" #c \
+                          ", 0\n\tv_mov_b32 v" #d ", 0\n\t"
+      TN_Z4(120, 121, 122, 123) TN_Z4(124, 125, 126, 127) TN_Z4(128, 129, 130, 131)
+      TN_Z4(132, 133, 134, 135) TN_Z4(136, 137, 138, 139) TN_Z4(140, 141, 142, 143)
+      TN_Z4(144, 145, 146, 147) TN_Z4(148, 149, 150, 151) TN_Z4(216, 217, 218, 219)
+      TN_Z4(220, 221, 222, 223) TN_Z4(224, 225, 226, 227) TN_Z4(228, 229, 230, 231)
+      TN_Z4(232, 233, 234, 235) TN_Z4(236, 237, 238, 239) TN_Z4(240, 241, 242, 243)
+      TN_Z4(244, 245, 246, 247)
+#undef TN_Z4
+      "s_nop 0");
+}
 
 __device__ __forceinline__ float cppn_slope(int act, float v, float z) {
   switch (act) {
@@ -349,29 +422,39 @@ __device__ __forceinline__ float cppn_slope(int act, float v, float z) {
 // respect to the CPPN's connection weights and node biases, where the upstream
 // u_q is dw1t / dw2t at the query when its weight survived the threshold (the
 // CPPN value of this very evaluation, float32) and 0 otherwise. Each lane runs
-// the CPPN forward at its query (values and pre-activations kept by position),
-// then the reverse sweep:
+// the CPPN forward at one query of each of the wavefront's two tiles (values
+// and pre-activations kept by position), then the reverse sweep:
 //   delta_k = gbar_k act'(z_k);  db_k += delta_k;
 //   for in-edge e = (j -> k): dt = delta_k rho_k (/ n for mean);
 //   dw_e += dt v_j;  gbar_j += dt w_e
-// accumulating over all its queries; at the end every sum is reduced over the
-// wavefront and written to this wavefront's slot of `part`. Sum and mean
-// aggregation only (the CPPN's); other genomes get NaN.
-__global__ __launch_bounds__(256) void cppn_backward_kernel(
-    PopView pop, const int32_t* __restrict__ status, const int32_t* __restrict__ n_valid,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ edge_src,
-    const int32_t* __restrict__ w_bits, const int32_t* __restrict__ fn,
-    const int32_t* __restrict__ bias_bits, const int32_t* __restrict__ resp_bits,
-    const int32_t* __restrict__ io_pos, SubGeom sg, int n_chunks, int per_wave,
-    const float* __restrict__ dw1t, const float* __restrict__ dw2t, float* __restrict__ part) {
+// The per-lane sums (both tiles' terms added first) accumulate in LDS, one
+// slot per lane and sum (read, add, write: a wavefront's LDS operations
+// complete in order, so each sum runs in program order); at the end every
+// slot is reduced over the wavefront in a fixed order and written to this
+// wavefront's slot of `part`.
+// Sum and mean aggregation only (the CPPN's); other genomes get NaN.
+constexpr int kCppnWaves = 2, kCppnUnitsPerWave = 32, kCppnUnit = 2 * kWave;
+
+__global__ __launch_bounds__(kWave * kCppnWaves) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
+cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
+                     const int32_t* __restrict__ n_valid, const int32_t* __restrict__ row_ptr,
+                     const int32_t* __restrict__ edge_src, const int32_t* __restrict__ w_bits,
+                     const int32_t* __restrict__ fn, const int32_t* __restrict__ bias_bits,
+                     const int32_t* __restrict__ resp_bits, const int32_t* __restrict__ io_pos,
+                     SubGeom sg, int n_chunks, const float* __restrict__ dw1t,
+                     const float* __restrict__ dw2t, float* __restrict__ part) {
+  adj_reserve();
+  __shared__ float acc_all[kCppnWaves * kCppnPart * kWave];
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
   const int g = blockIdx.x / n_chunks;
   const int chunk = blockIdx.x - g * n_chunks;
   float* out = part + ((int64_t)g * n_chunks * W + (int64_t)chunk * W + wave) * kCppnPart;
+  float* acc = acc_all + wave * kCppnPart * kWave + lane;  // slot i at acc[i * kWave]
   const int n = n_valid[g];
-  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
+  const int64_t nb = uniform64(pop.node_base(g)), cb = uniform64(pop.conn_base(g)),
+                rb = uniform64(pop.rowptr_base(g));
   const int32_t* rp = row_ptr + rb;
   const int n_edges = n > 0 ? rp[n] : 0;
   const int nio = pop.n_in + pop.n_out;
@@ -386,98 +469,127 @@ __global__ __launch_bounds__(256) void cppn_backward_kernel(
     for (int i = lane; i < kCppnPart; i += kWave) out[i] = __builtin_nanf("");
     return;
   }
-  const int32_t* fnp = fn + nb;
-  const int32_t* bp = bias_bits + nb;
-  const int32_t* rsp = resp_bits + nb;
-  const int32_t* srcp = edge_src + cb;
-  const int32_t* wp = w_bits + cb;
-  const int Q1 = sg.S * sg.S, Q = Q1 + sg.S * sg.n_out;
-  const int n_tiles = (Q + kWave - 1) / kWave;
-  const int t0 = (chunk * W + wave) * per_wave;
-  const int t1 = min(t0 + per_wave, n_tiles);
-  f32x32 acc_db = 0.0f, acc_w0 = 0.0f, acc_w1 = 0.0f;
-  for (int t = t0; t < t1; ++t) {
-    const int q = t * kWave + lane;
-    const bool live = q < Q;
-    const bool first = q < Q1;
-    const int qq = first ? q : q - Q1;
-    const int tgt = qq / sg.S;
-    const int src = qq - tgt * sg.S;
-    const int rs = src / sg.grid, cs = src - rs * sg.grid;
-    float in[5];
-    in[0] = fmaf((float)cs, sg.step, -1.0f);
-    in[1] = fmaf((float)rs, sg.step, -1.0f);
-    if (first) {
-      const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
-      in[2] = fmaf((float)ct, sg.step, -1.0f);
-      in[3] = fmaf((float)rt, sg.step, -1.0f);
-    } else {
-      in[2] = sg.n_out > 1 ? fmaf((float)tgt, sg.ostep, -1.0f) : 0.0f;
-      in[3] = 0.0f;
+  for (int i = 0; i < kCppnPart; ++i) acc[i * kWave] = 0.0f;
+  // the genome's program across the wavefront, read once: lane p holds
+  // position p's function word, bias, response and first in-edge (lane n the
+  // end of the last), lane e edge e's source position and weight; the sweeps
+  // below take every field with v_readlane instead of a memory load
+  const int l_fn = lane < n ? fn[nb + lane] : 0;
+  const int l_bias = lane < n ? bias_bits[nb + lane] : 0;
+  const int l_resp = lane < n ? resp_bits[nb + lane] : 0;
+  const int l_rp = lane <= n ? rp[lane] : 0;
+  const int l_src = lane < n_edges ? edge_src[cb + lane] : 0;
+  const int l_w = lane < n_edges ? w_bits[cb + lane] : 0;
+  const int Q1 = sg.S * sg.S, Q2 = sg.S * sg.n_out, Q = Q1 + Q2;
+  const int n_units = (Q + kCppnUnit - 1) / kCppnUnit;
+  const int u0 = (chunk * W + wave) * kCppnUnitsPerWave;
+  const int u1 = min(u0 + kCppnUnitsPerWave, n_units);
+  for (int u = u0; u < u1; ++u) {
+    const bool first = u * kCppnUnit < Q1;  // S*S is a multiple of 4096
+    const int base = first ? u * kCppnUnit : u * kCppnUnit - Q1;
+    float in[2][5], up[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int qq = base + k * kWave + lane;
+      const int tgt = qq / sg.S;
+      const int src = qq - tgt * sg.S;
+      const int rs = src / sg.grid, cs = src - rs * sg.grid;
+      in[k][0] = fmaf((float)cs, sg.step, -1.0f);
+      in[k][1] = fmaf((float)rs, sg.step, -1.0f);
+      if (first) {
+        const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
+        in[k][2] = fmaf((float)ct, sg.step, -1.0f);
+        in[k][3] = fmaf((float)rt, sg.step, -1.0f);
+        up[k] = dw1t[(int64_t)g * Q1 + qq];
+      } else {
+        in[k][2] = sg.n_out > 1 ? fmaf((float)tgt, sg.ostep, -1.0f) : 0.0f;
+        in[k][3] = 0.0f;
+        up[k] = qq < Q2 ? dw2t[(int64_t)g * Q2 + qq] : 0.0f;
+      }
+      in[k][4] = 1.0f;
     }
-    in[4] = 1.0f;
-    const float up = live ? (first ? dw1t[(int64_t)g * Q1 + qq]
-                                   : dw2t[(int64_t)g * sg.S * sg.n_out + qq])
-                          : 0.0f;
     // forward, values and pre-activations by position
-    f32x32 v = 0.0f, z = 0.0f;
-    asm volatile("" : "+v"(v), "+v"(z));
     for (int p = 0; p < n; ++p) {
-      const int f = fnp[p];
+      const int f = __builtin_amdgcn_readlane(l_fn, p);
       if (f < 0) {
-        const int k = (f >> 16) & 0x7fff;
-        const float x = k == 0 ? in[0] : k == 1 ? in[1] : k == 2 ? in[2] : k == 3 ? in[3] : in[4];
-        bset(v, p, x);
+        const int i = (f >> 16) & 0x7fff;
+        float x[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          x[k] = i == 0 ? in[k][0] : i == 1 ? in[k][1] : i == 2 ? in[k][2] : i == 3 ? in[k][3]
+                                                                                 : in[k][4];
+        adj_set_v(p, x[0], x[1]);
         continue;
       }
-      const int e0 = rp[p], e1 = rp[p + 1];
-      float sum = 0.0f;
-      for (int e = e0; e < e1; ++e) sum = fmaf(__int_as_float(wp[e]), bget(v, srcp[e]), sum);
-      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) sum = sum / (float)(e1 - e0);
-      const float zz[1] = {fmaf(__int_as_float(rsp[p]), sum, __int_as_float(bp[p]))};
-      float vv[1];
-      activate_all<1>(f & 0xff, zz, vv);
-      bset(v, p, vv[0]);
-      bset(z, p, zz[0]);
-    }
-    const float y = bget(v, op);
-    const float u = fabsf(y) >= sg.thr ? up : 0.0f;  // NaN y: no gradient
-    // reverse sweep
-    f32x32 gb = 0.0f;
-    asm volatile("" : "+v"(gb));
-    bset(gb, op, u);
-    for (int p = n - 1; p >= 0; --p) {
-      const int f = fnp[p];
-      if (f < 0) continue;
-      const float delta = bget(gb, p) * cppn_slope(f & 0xff, bget(v, p), bget(z, p));
-      bset(acc_db, p, bget(acc_db, p) + delta);
-      const int e0 = rp[p], e1 = rp[p + 1];
-      float dt = delta * __int_as_float(rsp[p]);
-      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) dt = dt / (float)(e1 - e0);
+      const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
+      float s0 = 0.0f, s1 = 0.0f;
       for (int e = e0; e < e1; ++e) {
-        const int j = srcp[e];
-        if (e < 32)
-          bset(acc_w0, e, fmaf(dt, bget(v, j), bget(acc_w0, e)));
-        else
-          bset(acc_w1, e - 32, fmaf(dt, bget(v, j), bget(acc_w1, e - 32)));
-        bset(gb, j, fmaf(dt, __int_as_float(wp[e]), bget(gb, j)));
+        const int j = __builtin_amdgcn_readlane(l_src, e);
+        adj_fma_v(s0, s1, __int_as_float(__builtin_amdgcn_readlane(l_w, e)), j);
+      }
+      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) {
+        s0 = s0 / (float)(e1 - e0);
+        s1 = s1 / (float)(e1 - e0);
+      }
+      const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));
+      const float bias = __int_as_float(__builtin_amdgcn_readlane(l_bias, p));
+      const float z[2] = {fmaf(rho, s0, bias), fmaf(rho, s1, bias)};
+      float v[2];
+      activate_all<2>(f & 0xff, z, v);
+      adj_set_vz(p, v[0], v[1], z[0], z[1]);
+    }
+    float y0, y1;
+    adj_get_v(op, y0, y1);
+    // NaN y: no gradient
+    adj_zero_g();
+    adj_set_g(op, fabsf(y0) >= sg.thr ? up[0] : 0.0f, fabsf(y1) >= sg.thr ? up[1] : 0.0f);
+    // reverse sweep
+    for (int p = n - 1; p >= 0; --p) {
+      const int f = __builtin_amdgcn_readlane(l_fn, p);
+      if (f < 0) continue;
+      float g0, g1, v0, v1, z0, z1;
+      adj_get_gvz(p, g0, g1, v0, v1, z0, z1);
+      const int act = f & 0xff;
+      const float d0 = g0 * cppn_slope(act, v0, z0), d1 = g1 * cppn_slope(act, v1, z1);
+      acc[(kCppnEdges + p) * kWave] += d0 + d1;
+      const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
+      const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));
+      float dt0 = d0 * rho, dt1 = d1 * rho;
+      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) {
+        dt0 = dt0 / (float)(e1 - e0);
+        dt1 = dt1 / (float)(e1 - e0);
+      }
+      // two in-edges per step (their sources differ, so the two updates of
+      // G are independent); the fields of both are read before either window
+      int e = e0;
+      for (; e + 1 < e1; e += 2) {
+        const float oa = acc[e * kWave], ob = acc[(e + 1) * kWave];  // loads issued first
+        const int ja = __builtin_amdgcn_readlane(l_src, e);
+        const int jb = __builtin_amdgcn_readlane(l_src, e + 1);
+        const float wa = __int_as_float(__builtin_amdgcn_readlane(l_w, e));
+        const float wb = __int_as_float(__builtin_amdgcn_readlane(l_w, e + 1));
+        float ta0, ta1, tb0, tb1;
+        adj_get_v(ja, ta0, ta1);
+        adj_get_v(jb, tb0, tb1);
+        adj_fma_g(ja, dt0, dt1, wa);
+        adj_fma_g(jb, dt0, dt1, wb);
+        acc[e * kWave] = oa + fmaf(dt1, ta1, dt0 * ta0);
+        acc[(e + 1) * kWave] = ob + fmaf(dt1, tb1, dt0 * tb0);
+      }
+      if (e < e1) {
+        const float o = acc[e * kWave];
+        const int j = __builtin_amdgcn_readlane(l_src, e);
+        float t0, t1;
+        adj_get_v(j, t0, t1);
+        adj_fma_g(j, dt0, dt1, __int_as_float(__builtin_amdgcn_readlane(l_w, e)));
+        acc[e * kWave] = o + fmaf(dt1, t1, dt0 * t0);
       }
     }
   }
   // one reduction over the wavefront per sum, fixed order
-#pragma unroll
-  for (int e = 0; e < 32; ++e) {
-    const float a0 = wave_sum(acc_w0[e]);
-    const float a1 = wave_sum(acc_w1[e]);
-    if (lane == 0) {
-      out[e] = a0;
-      out[32 + e] = a1;
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < 32; ++p) {
-    const float d = wave_sum(acc_db[p]);
-    if (lane == 0) out[kCppnEdges + p] = d;
+  for (int i = 0; i < kCppnPart; ++i) {
+    const float t = wave_sum(acc[i * kWave]);
+    if (lane == 0) out[i] = t;
   }
 }
 
@@ -625,13 +737,11 @@ int launch_substrate_backward(const tn_substrate& sub, int P, const uint16_t* w2
 }
 
 namespace {
-constexpr int kCppnWaves = 4, kCppnTilesPerWave = 64;
-
 int cppn_chunks(const tn_substrate& sub) {
   const int64_t S = (int64_t)sub.grid * sub.grid;
-  const int64_t n_tiles = (S * S + S * sub.n_out + kWave - 1) / kWave;
-  const int64_t per_wg = (int64_t)kCppnWaves * kCppnTilesPerWave;
-  return (int)((n_tiles + per_wg - 1) / per_wg);
+  const int64_t n_units = (S * S + S * sub.n_out + kCppnUnit - 1) / kCppnUnit;
+  const int64_t per_wg = (int64_t)kCppnWaves * kCppnUnitsPerWave;
+  return (int)((n_units + per_wg - 1) / per_wg);
 }
 }  // namespace
 
@@ -659,7 +769,7 @@ int launch_cppn_backward(const tn_population& p, const tn_transformed& t, const 
                      reinterpret_cast<const int32_t*>(t.edge_w), t.pos_fn,
                      reinterpret_cast<const int32_t*>(t.pos_bias),
                      reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, sg, n_chunks,
-                     kCppnTilesPerWave, dw1t, dw2t, part);
+                     dw1t, dw2t, part);
   int rc = check_launch();
   if (rc != TN_OK) return rc;
   hipLaunchKernelGGL(cppn_grad_reduce_kernel, dim3((unsigned)p.P), dim3(256), 0, stream,
