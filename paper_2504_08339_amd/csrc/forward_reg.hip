@@ -35,6 +35,8 @@ struct RegArgs {
   const int32_t* genomes;  // genome list (nullptr: every genome, in order)
   int32_t* queue;          // persistent form: next item to take
   int n_items;             // grid form: list length * n_groups; persistent: * n_tiles
+  int in_phase;            // register file: tiles of inputs staged per LDS-direct round (0: chunks)
+  int stage_stride;        // floats of LDS staging per wavefront
 };
 
 // Observations and outputs pass through LDS in chunks of up to kChunk
@@ -44,6 +46,48 @@ constexpr int kChunk = 8;
 constexpr int kStage = kWave * (kChunk + 1);  // floats per tile
 // staging regions per wavefront of variant V
 constexpr int stage_tiles(int V) { return V >= 32 ? rf_tiles(V) : 1; }
+
+// The register-file form stages a unit's observations with LDS-direct loads
+// (global_load_lds: memory to LDS without passing through registers, so a
+// whole round is in flight at once and waited for once), in rounds of as many
+// of the unit's tiles as fit this many bytes per wavefront (two wavefronts per
+// SIMD then still fit the compute unit's LDS), one tile per round at least.
+constexpr int kDmaBytes = 20 * 1024;
+
+// Tiles per LDS-direct round for variant V and I inputs (0: the bank forms,
+// which stage in chunks of kChunk columns through registers).
+int dma_phase(int V, int I) {
+  if (V < 32) return 0;
+  int P = rf_tiles(V);
+  while (P > 1 && (int64_t)P * kWave * I * 4 > kDmaBytes) P /= 2;
+  return P;
+}
+// LDS staging floats per wavefront.
+int stage_floats(int V, int I) {
+  const int P = dma_phase(V, I);
+  return std::max(kStage * stage_tiles(V), P * kWave * I);
+}
+
+// Rows r of register files f0 .. f0 + P - 1 := x[0 .. P-1] (P = K: one window
+// for all; two of four: one window for the pair; else one window each).
+template <int R>
+__device__ __forceinline__ void rf_set_part(int P, int f0, int r, const float (&x)[rf_tiles(R)]) {
+  constexpr int K = rf_tiles(R);
+  if (P == K) {
+    rfk_set<R>(r, x);
+  } else if (K == 4 && P == 2) {
+    if (f0 == 0)
+      asm volatile("s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
+                   "v_mov_b32 v106, %1\n\ts_set_gpr_idx_off" ::"v"(x[0]),
+                   "v"(x[1]), "s"(r) : "m0");
+    else
+      asm volatile("s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v156, %0\n\t"
+                   "v_mov_b32 v206, %1\n\ts_set_gpr_idx_off" ::"v"(x[0]),
+                   "v"(x[1]), "s"(r) : "m0");
+  } else {
+    for (int p = 0; p < P; ++p) rf_set((f0 + p) * R + r, x[p]);
+  }
+}
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   constexpr int kXcd = 8;
@@ -124,7 +168,7 @@ __device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
 // to all tiles under one window per input; outputs leave the same way.
 template <int R, bool kLoss>
 __device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
-                                          const int2* __restrict__ pe, int nn,
+                                          const int2* __restrict__ pe, int nn, int in_phase,
                                           const int4* __restrict__ pn,
                                           const int32_t* __restrict__ out_pos, int orow_first,
                                           int I, int O, int b0, int B,
@@ -134,38 +178,27 @@ __device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
   int nbat[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) nbat[k] = max(0, min(kWave, B - b0 - k * kWave));
-  for (int c0 = 0; c0 < I; c0 += kChunk) {
-    const int ch = min(kChunk, I - c0);
-    const int sr = ch | 1;
+  {
+    // rounds of in_phase tiles: the tiles' observations are contiguous in
+    // memory (64 * in_phase * I floats), copied verbatim into LDS with one
+    // LDS-direct load per 64 floats, waited for once, then read back one
+    // column per row (stride I per lane)
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // earlier LDS use is done
+    for (int f0 = 0; f0 < K; f0 += in_phase) {
+      const int nobs = max(0, min(in_phase * kWave, B - b0 - f0 * kWave));
+      const int total = nobs * I;
+      const float* src = xg + (int64_t)(b0 + f0 * kWave) * I;
+      for (int j = 0; j < total; j += kWave)
+        if (j + lane < total) __builtin_amdgcn_global_load_lds(src + j + lane, stg + j, 4, 0, 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      for (int c = 0; c < I; ++c) {
+        float x[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int tot = nbat[k] * ch;
-      const float* xo = xg + (int64_t)(b0 + k * kWave) * I;
-      float* sk = stg + k * kStage;
-      DivWalk dw(lane, ch, kWave);
-      for (int i0 = 0; i0 < tot; i0 += 8 * kWave) {
-        float t[8];
-        int o[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const bool ok = i0 + u * kWave + lane < tot;
-          o[u] = ok ? dw.b * sr + dw.c : -1;
-          t[u] = ok ? xo[(int64_t)dw.b * I + c0 + dw.c] : 0.0f;
-          dw.step();
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (o[u] >= 0) sk[o[u]] = t[u];
+        for (int p = 0; p < K; ++p) x[p] = p < in_phase ? stg[(p * kWave + lane) * I + c] : 0.0f;
+        rf_set_part<R>(in_phase, f0, c, x);
       }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // reads done before the next round
     }
-    wave_sync();
-    for (int j = 0; j < ch; ++j) {
-      float x[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = stg[k * kStage + lane * sr + j];
-      rfk_set<R>(c0 + j, x);
-    }
-    wave_sync();
   }
   walk_records<R>(rec, pe, nn, lane);
   float sse = 0.0f;
@@ -251,7 +284,7 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
     const float* xg = obs + (int64_t)g * a.obs_stride;
     const float* tg = kLoss ? target + (int64_t)g * a.target_stride : nullptr;
     if constexpr (NB >= 32) {
-      sse += run_unit<NB, kLoss>(rec, pe, nn, pn, out_pos, orow_first, I, O, b0, a.B, xg, yg,
+      sse += run_unit<NB, kLoss>(rec, pe, nn, a.in_phase, pn, out_pos, orow_first, I, O, b0, a.B, xg, yg,
                                  tg, stg, lane);
     } else {
       const float* xo = xg + (int64_t)b0 * I;
@@ -348,7 +381,7 @@ forward_rf_kernel(TN_REG_PARAMS, float* __restrict__ loss) {
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage * rf_tiles(R);
+  float* stg = stage_all + wave * a.stage_stride;
   int entry, t_begin, t_end, t_step;
   if (kLoss) {
     entry = blockIdx.x;
@@ -386,7 +419,7 @@ forward_rf_queue_kernel(TN_REG_PARAMS) {
   __shared__ int base_sh;
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage * rf_tiles(R);
+  float* stg = stage_all + wave * a.stage_stride;
   for (;;) {
     if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
     __syncthreads();
@@ -413,7 +446,7 @@ int launch_grid(const tn_population& p, const tn_transformed& t, const float* ob
                 const float* target, float* loss, const RegArgs& a, int grid, int waves,
                 hipStream_t stream) {
   if (grid == 0) return TN_OK;
-  const size_t lds = sizeof(float) * (size_t)kStage * stage_tiles(V) * waves;
+  const size_t lds = sizeof(float) * (size_t)a.stage_stride * waves;
 #define TN_REG_LAUNCH(K)                                                                    \
   hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
                      t.status, t.prog_rows, t.n_valid,                                        \
@@ -441,7 +474,7 @@ template <int V>
 int launch_queue(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                  const RegArgs& a, int grid, int waves, hipStream_t stream) {
   if (grid == 0) return TN_OK;
-  const size_t lds = sizeof(float) * (size_t)kStage * stage_tiles(V) * waves;
+  const size_t lds = sizeof(float) * (size_t)a.stage_stride * waves;
 #define TN_REG_LAUNCH(K)                                                                    \
   hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
                      t.status, t.prog_rows, t.n_valid,                                        \
@@ -484,7 +517,8 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
   const int kt = stage_tiles(variant);
   const int n_tiles = ((B + kWave - 1) / kWave + kt - 1) / kt;
   RegArgs a{obs_stride, B,  0, 0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.rows_lo,
-            tile.skip_above ? 1 : 0, work.genomes, work.queue, 0};
+            tile.skip_above ? 1 : 0, work.genomes, work.queue, 0, dma_phase(variant, p.n_in),
+            stage_floats(variant, p.n_in)};
   if (work.queue) {
     a.n_items = n_list * n_tiles;
     // items per wavefront per grab: about 4 grabs per resident workgroup
@@ -522,13 +556,13 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
   if (waves > 8) return TN_EINVAL;
   const int n_tiles = (B + kWave - 1) / kWave;
   RegArgs a{obs_stride, B,  target_stride, scale,   offset, n_tiles, 1, n_tiles, 64, -1,
-            skip_above ? 1 : 0, nullptr, nullptr, 0};
+            skip_above ? 1 : 0, nullptr, nullptr, 0, 0, stage_floats(0, p.n_in)};
   return launch_grid<0, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
 }
 
-int reg_queue_grid(int variant, int waves) {
+int reg_queue_grid(int variant, int waves, int n_in) {
   int dev = 0, cus = 0, per_cu = 0;
-  const size_t lds = sizeof(float) * kStage * stage_tiles(variant) * waves;
+  const size_t lds = sizeof(float) * (size_t)stage_floats(variant, n_in) * waves;
   const void* k = nullptr;
   switch (variant) {
 #define TN_CASE(V) \

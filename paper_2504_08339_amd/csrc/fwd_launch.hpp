@@ -60,7 +60,7 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
                             float* loss, int waves, bool skip_above, hipStream_t stream);
 // Resident workgroups (whole device) of the persistent register kernel of a
 // variant (0, 1, 2 banks or register-file rows).
-int reg_queue_grid(int variant, int waves);
+int reg_queue_grid(int variant, int waves, int n_in);
 
 int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,
                    int64_t obs_stride, int B, float* out, const LdsTile& tile,

@@ -37,20 +37,20 @@ __device__ __forceinline__ float rf_get(int r) {
   asm volatile("s_set_gpr_idx_on %1, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, " TN_RF_V0
                "\n\ts_set_gpr_idx_off"
                : "=v"(x)
-               : "s"(r));
+               : "s"(r) : "m0");
   return x;
 }
 __device__ __forceinline__ void rf_set(int r, float x) {
   asm volatile("s_set_gpr_idx_on %1, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 " TN_RF_V0
                ", %0\n\ts_set_gpr_idx_off" ::"v"(x),
-               "s"(r));
+               "s"(r) : "m0");
 }
 // acc += w * row[r] in one instruction.
 __device__ __forceinline__ void rf_fma(float& acc, float w, int r) {
   asm volatile("s_set_gpr_idx_on %2, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %1, " TN_RF_V0
                "\n\ts_set_gpr_idx_off"
                : "+v"(acc)
-               : "s"(w), "s"(r));
+               : "s"(w), "s"(r) : "m0");
 }
 
 // Observation tiles held per wavefront by a register file of R rows per tile:
@@ -87,14 +87,14 @@ __device__ __forceinline__ void rfk_fma(float (&acc)[rf_tiles(R)], float w, int 
         "s_set_gpr_idx_on %3, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %2, v56\n\t"
         "v_fmac_f32 %1, %2, v156\n\ts_set_gpr_idx_off"
         : "+v"(acc[0]), "+v"(acc[1])
-        : "s"(w), "s"(r));
+        : "s"(w), "s"(r) : "m0");
   } else {
     asm volatile(
         "s_set_gpr_idx_on %5, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %4, v56\n\t"
         "v_fmac_f32 %1, %4, v106\n\tv_fmac_f32 %2, %4, v156\n\t"
         "v_fmac_f32 %3, %4, v206\n\ts_set_gpr_idx_off"
         : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
-        : "s"(w), "s"(r));
+        : "s"(w), "s"(r) : "m0");
   }
 }
 
@@ -107,13 +107,13 @@ __device__ __forceinline__ void rfk_set(int r, const float (&x)[rf_tiles(R)]) {
     asm volatile(
         "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
         "v_mov_b32 v156, %1\n\ts_set_gpr_idx_off" ::"v"(x[0]),
-        "v"(x[1]), "s"(r));
+        "v"(x[1]), "s"(r) : "m0");
   } else {
     asm volatile(
         "s_set_gpr_idx_on %4, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
         "v_mov_b32 v106, %1\n\tv_mov_b32 v156, %2\n\tv_mov_b32 v206, %3\n\t"
         "s_set_gpr_idx_off" ::"v"(x[0]),
-        "v"(x[1]), "v"(x[2]), "v"(x[3]), "s"(r));
+        "v"(x[1]), "v"(x[2]), "v"(x[3]), "s"(r) : "m0");
   }
 }
 
@@ -127,14 +127,14 @@ __device__ __forceinline__ void rfk_get(int r, float (&x)[rf_tiles(R)]) {
         "s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v56\n\t"
         "v_mov_b32 %1, v156\n\ts_set_gpr_idx_off"
         : "=v"(x[0]), "=v"(x[1])
-        : "s"(r));
+        : "s"(r) : "m0");
   } else {
     asm volatile(
         "s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v56\n\t"
         "v_mov_b32 %1, v106\n\tv_mov_b32 %2, v156\n\tv_mov_b32 %3, v206\n\t"
         "s_set_gpr_idx_off"
         : "=v"(x[0]), "=v"(x[1]), "=v"(x[2]), "=v"(x[3])
-        : "s"(r));
+        : "s"(r) : "m0");
   }
 }
 
@@ -357,10 +357,10 @@ struct LaneRec {
 // The register-file walk over the 16-word records of the non-input positions
 // (tn_transformed.prog_rec), in topological order, for every tile of the
 // wavefront. The records come four at a time with one coalesced vector load
-// (64 lanes x one word), the next block requested as the current one starts:
-// vector loads complete in order, so that load overlaps four nodes of work
-// without holding anything else up, and its words reach the scalar unit
-// through v_readlane with constant lane indexes. Lanes past the genome's last
+// (64 lanes x one word), each block requested two blocks ahead: vector loads
+// complete in order, so that load overlaps eight nodes of work without holding
+// anything else up, and its words reach the scalar unit through v_readlane
+// with constant lane indexes. Lanes past the genome's last
 // record read its last word instead (no load past the genome's records).
 template <int R>
 __device__ __forceinline__ void walk_records(const int32_t* __restrict__ rec,
@@ -368,8 +368,9 @@ __device__ __forceinline__ void walk_records(const int32_t* __restrict__ rec,
   if (nn <= 0) return;
   const int lim = nn * 16 - 1;
   int cur = rec[min(lane, lim)];
+  int nx1 = rec[min(kWave + lane, lim)];
   for (int q = 0; q < nn; q += 4) {
-    const int nxt = rec[min(q * 16 + kWave + lane, lim)];
+    const int nx2 = rec[min(q * 16 + 2 * kWave + lane, lim)];
     rf_node<R>(LaneRec<0>{cur}, pe);
     if (q + 1 < nn) {
       rf_node<R>(LaneRec<1>{cur}, pe);
@@ -378,7 +379,8 @@ __device__ __forceinline__ void walk_records(const int32_t* __restrict__ rec,
         if (q + 3 < nn) rf_node<R>(LaneRec<3>{cur}, pe);
       }
     }
-    cur = nxt;
+    cur = nx1;
+    nx1 = nx2;
   }
 }
 

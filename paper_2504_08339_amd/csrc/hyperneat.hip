@@ -343,28 +343,28 @@ __device__ __forceinline__ void adj_fma_v(float& s0, float& s1, float w, int j) 
       "s_set_gpr_idx_on %3, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %2, v56\n\t"
       "v_fmac_f32 %1, %2, v152\n\ts_set_gpr_idx_off"
       : "+v"(s0), "+v"(s1)
-      : "s"(w), "s"(j));
+      : "s"(w), "s"(j) : "m0");
 }
 // V[p] := v{0,1}
 __device__ __forceinline__ void adj_set_v(int p, float v0, float v1) {
   asm volatile(
       "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
       "v_mov_b32 v152, %1\n\ts_set_gpr_idx_off" ::"v"(v0),
-      "v"(v1), "s"(p));
+      "v"(v1), "s"(p) : "m0");
 }
 // V[p] := v{0,1}, Z[p] := z{0,1}
 __device__ __forceinline__ void adj_set_vz(int p, float v0, float v1, float z0, float z1) {
   asm volatile(
       "s_set_gpr_idx_on %4, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v56, %0\n\t"
       "v_mov_b32 v152, %1\n\tv_mov_b32 v88, %2\n\tv_mov_b32 v184, %3\n\ts_set_gpr_idx_off" ::"v"(v0),
-      "v"(v1), "v"(z0), "v"(z1), "s"(p));
+      "v"(v1), "v"(z0), "v"(z1), "s"(p) : "m0");
 }
 // G[p] := g{0,1}
 __device__ __forceinline__ void adj_set_g(int p, float g0, float g1) {
   asm volatile(
       "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v120, %0\n\t"
       "v_mov_b32 v216, %1\n\ts_set_gpr_idx_off" ::"v"(g0),
-      "v"(g1), "s"(p));
+      "v"(g1), "s"(p) : "m0");
 }
 // t{0,1} := V[j]
 __device__ __forceinline__ void adj_get_v(int j, float& t0, float& t1) {
@@ -372,7 +372,7 @@ __device__ __forceinline__ void adj_get_v(int j, float& t0, float& t1) {
       "s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v56\n\t"
       "v_mov_b32 %1, v152\n\ts_set_gpr_idx_off"
       : "=v"(t0), "=v"(t1)
-      : "s"(j));
+      : "s"(j) : "m0");
 }
 // G[p], V[p], Z[p] of both tiles
 __device__ __forceinline__ void adj_get_gvz(int p, float& g0, float& g1, float& v0, float& v1,
@@ -382,14 +382,14 @@ __device__ __forceinline__ void adj_get_gvz(int p, float& g0, float& g1, float& 
       "v_mov_b32 %1, v216\n\tv_mov_b32 %2, v56\n\tv_mov_b32 %3, v152\n\t"
       "v_mov_b32 %4, v88\n\tv_mov_b32 %5, v184\n\ts_set_gpr_idx_off"
       : "=v"(g0), "=v"(g1), "=v"(v0), "=v"(v1), "=v"(z0), "=v"(z1)
-      : "s"(p));
+      : "s"(p) : "m0");
 }
 // G[j] += dt{0,1} * w, one indexed read-modify-write per tile
 __device__ __forceinline__ void adj_fma_g(int j, float dt0, float dt1, float w) {
   asm volatile(
       "s_set_gpr_idx_on %3, gpr_idx(SRC2,DST)\n\ts_nop 1\n\tv_fma_f32 v120, %0, %2, v120\n\t"
       "v_fma_f32 v216, %1, %2, v216\n\ts_set_gpr_idx_off" ::"v"(dt0),
-      "v"(dt1), "s"(w), "s"(j));
+      "v"(dt1), "s"(w), "s"(j) : "m0");
 }
 // G := 0 for both tiles (fixed registers, no window)
 __device__ __forceinline__ void adj_zero_g() {

@@ -83,7 +83,7 @@ int persistent_grid(const tn_plan& pl, const Bucket& b) {
     const int kt = tn::rf_tiles_of(b.rows_class);  // tiles per wavefront
     const int64_t items = (int64_t)b.count * (((pl.B + tn::kWave - 1) / tn::kWave + kt - 1) / kt);
     const int64_t need = (items + b.waves - 1) / b.waves;
-    return (int)std::min<int64_t>(tn::reg_queue_grid(b.rows_class, b.waves), need);
+    return (int)std::min<int64_t>(tn::reg_queue_grid(b.rows_class, b.waves, pl.pop.n_in), need);
   }
   return std::min(tn::lds_queue_grid(pl.pop, b.K, b.waves, b.max_rows), b.count);
 }
