@@ -288,12 +288,10 @@ def control(torch, tn, synth, args):
             torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"),
             torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"))
     tn.transform(dp, out=tr)
-    rows = int(tr.n_rows.max().item())
-    tile = dict(engine=tn.TN_ENGINE_LDS, obs_per_lane=4, waves_per_genome=4, rows=rows)
 
     def step(t):
         t("transform", tn.transform, dp, out=tr)
-        t("forward", tn.forward, dp, tr, obs, out=out, **tile)
+        t("forward", tn.forward, dp, tr, obs, out=out)
         t("distance", tn.distance, dp, workspace=ws, out=dist)
     step_ms, ms = timed_steps(torch, step, args.steps, args.warmup)
     nv, ne = genome_sizes(torch, pop, tr)
@@ -303,8 +301,9 @@ def control(torch, tn, synth, args):
     achieved = fwd_bytes / (ms["forward"] * 1e-3) / 1e9
     return {
         "workload": "control-policy: 1000 genomes, 17 -> 6, N_max 64, C_max 256, 1000 N(0,1) "
-                    "observations per genome; step = transform + forward (LDS engine, 4 obs "
-                    f"per lane, 4 waves, {rows} rows) + 1000 x 1000 compatibility distance",
+                    "observations per genome; step = transform + forward (the library's "
+                    "engine choice: register engine, four tiles of 64 observations per "
+                    "wavefront) + 1000 x 1000 compatibility distance",
         "value": pop.P * B / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
         "ms_per_step": step_ms, "call_ms": ms,
         "forward_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

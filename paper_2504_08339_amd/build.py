@@ -46,17 +46,24 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def _rf_base() -> int:
-    with open(os.path.join(CSRC, "fwd_reg.hpp")) as f:
-        m = re.search(r"#define TN_RF_BASE (\d+)", f.read())
+def _define(header: str, name: str) -> int:
+    with open(os.path.join(CSRC, header)) as f:
+        m = re.search(r"#define %s (\d+)" % name, f.read())
     if not m:
-        raise RuntimeError("TN_RF_BASE not found in fwd_reg.hpp")
+        raise RuntimeError(f"{name} not found in {header}")
     return int(m.group(1))
 
 
+def _rf_base(kernel: str) -> int:
+    """First VGPR of the register file of a register-file kernel."""
+    if "backward_rf_kernel" in kernel:
+        return _define("backward.hip", "TN_BW_RF_BASE")
+    return _define("fwd_reg.hpp", "TN_RF_BASE")
+
+
 # kernels that keep an explicit register file (names as they appear mangled)
-RF_KERNELS = ("forward_rf", "cppn_query_kernel", "cppn_backward_kernel")
-RF_SOURCES = ("forward_reg.hip", "hyperneat.hip")
+RF_KERNELS = ("forward_rf", "cppn_query_kernel", "cppn_backward_kernel", "backward_rf_kernel")
+RF_SOURCES = ("forward_reg.hip", "hyperneat.hip", "backward.hip")
 
 
 def check_register_file(src: str, extra=()) -> None:
@@ -65,7 +72,6 @@ def check_register_file(src: str, extra=()) -> None:
     compiler must never place a value there. Compiles `src` to AMDGPU assembly
     and fails if any instruction outside the inline-assembly blocks of a
     register-file kernel names such a VGPR (an SGPR spill lane, a temporary)."""
-    base = _rf_base()
     asm = os.path.join(BUILD, os.path.basename(src) + ".s")
     cmd = [hipcc(), *COMMON, *extra, "--cuda-device-only", "-S", src, "-o", asm]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -79,6 +85,7 @@ def check_register_file(src: str, extra=()) -> None:
         if not any(k in name for k in RF_KERNELS):
             continue
         checked += 1
+        base = _rf_base(name)
         end = heads[i + 1][0] if i + 1 < len(heads) else len(text)
         body = re.sub(r";;#ASMSTART.*?;;#ASMEND", "", text[pos:end], flags=re.S)
         for line in body.split("\n"):

@@ -127,6 +127,23 @@ __device__ float agg_partial(int agg, int e, int e0, int e1, const EdgeRec* edge
   return best == e ? 1.0f : 0.0f;
 }
 
+// Genomes the register-file adjoint (backward_rf_kernel, below) takes.
+constexpr int kRfPos = 48, kRfEdges = 64, kRfSlots = kRfEdges + kRfPos, kSlotRow = kWave + 1;
+// Its register file starts at v64 (the compiler keeps v0..v63: sin's argument
+// reduction needs the room): tile 0 at v64..v159, tile 1 at v160..v255, each
+// 96 rows, values at rows 0..47 and upstream gradients at rows 48..95.
+#define TN_BW_RF_BASE 64
+
+__device__ __forceinline__ bool rf_bwd_eligible(int st, int n, int n_edges, const int32_t* fnp) {
+  if (st || n > kRfPos || n_edges > kRfEdges) return false;
+  for (int p = 0; p < n; ++p) {
+    const int f = fnp[p];
+    const int agg = (f >> 8) & 0xff;
+    if (f >= 0 && agg != TN_AGG_SUM && agg != TN_AGG_MEAN) return false;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(kWave) void backward_kernel(
     PopView pop, const int32_t* __restrict__ status, const int32_t* __restrict__ n_valid,
     const int32_t* __restrict__ order, const int32_t* __restrict__ row_ptr,
@@ -151,6 +168,10 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
   float* v = reinterpret_cast<float*>(lds + L.v_off);
   float* gr = reinterpret_cast<float*>(lds + L.g_off);
 
+  {
+    const int n0 = n_valid[g];
+    if (rf_bwd_eligible(st, n0, st ? 0 : row_ptr[rb + n0], fn + nb)) return;  // backward_rf_kernel's
+  }
   if (st) {
     const float nan = __builtin_nanf("");
     for (int64_t r = lane; r < crows; r += kWave) a.dW[cb + r] = nan;
@@ -284,6 +305,262 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
   }
 }
 
+// ------------------------------------------------ register-file adjoint
+//
+// The same derivative for the genomes that fit it (tn_backward runs both
+// kernels; each takes the genomes the other leaves): at most kRfPos positions
+// and kRfEdges in-edges, sum or mean aggregation only, not flagged. One
+// wavefront per genome, lane = observation, two tiles of 64 observations per
+// step. Values and upstream gradients live in registers indexed by position
+// (two files of 96 rows, values at rows 0..47 and gradients at rows 48..95);
+// the genome's program is held across the lanes (read with v_readlane). Per
+// step:
+//   forward: v_p = act(bias + resp * agg(w_e v_src)) at every non-input
+//     position (gradient row cleared in the same window);
+//   outputs: gbar_out += dL/dy;
+//   reverse: delta_p = gbar_p act'(z_p) (z re-evaluated for sin, gaussian,
+//     abs); db_p += delta_p; dt = delta_p resp (/ n for mean); per in-edge
+//     dW_e += dt v_src and gbar_src += dt w_e (one indexed read-modify-write).
+// The per-observation terms (both tiles added first) accumulate per lane in
+// LDS slots (row stride 65: conflict free), each in program order; at the end
+// lane s sums slot s over the 64 lanes in lane order. Deterministic.
+// V[p] := v{0,1}, G[p] := 0
+__device__ __forceinline__ void bw_set_v(int p, float v0, float v1) {
+  asm volatile(
+      "s_set_gpr_idx_on %2, gpr_idx(DST)\n\ts_nop 1\n\tv_mov_b32 v64, %0\n\t"
+      "v_mov_b32 v160, %1\n\tv_mov_b32 v112, 0\n\tv_mov_b32 v208, 0\n\ts_set_gpr_idx_off" ::"v"(v0),
+      "v"(v1), "s"(p)
+      : "m0");
+}
+// t{0,1} := V[j]
+__device__ __forceinline__ void bw_get_v(int j, float& t0, float& t1) {
+  asm volatile(
+      "s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v64\n\t"
+      "v_mov_b32 %1, v160\n\ts_set_gpr_idx_off"
+      : "=v"(t0), "=v"(t1)
+      : "s"(j)
+      : "m0");
+}
+// s{0,1} += w * V[j]
+__device__ __forceinline__ void bw_fma_v(float& s0, float& s1, float w, int j) {
+  asm volatile(
+      "s_set_gpr_idx_on %3, gpr_idx(SRC1)\n\ts_nop 1\n\tv_fmac_f32 %0, %2, v64\n\t"
+      "v_fmac_f32 %1, %2, v160\n\ts_set_gpr_idx_off"
+      : "+v"(s0), "+v"(s1)
+      : "s"(w), "s"(j)
+      : "m0");
+}
+// G[p], V[p] of both files
+__device__ __forceinline__ void bw_get_gv(int p, float& g0, float& g1, float& v0, float& v1) {
+  asm volatile(
+      "s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\ts_nop 1\n\tv_mov_b32 %0, v112\n\t"
+      "v_mov_b32 %1, v208\n\tv_mov_b32 %2, v64\n\tv_mov_b32 %3, v160\n\ts_set_gpr_idx_off"
+      : "=v"(g0), "=v"(g1), "=v"(v0), "=v"(v1)
+      : "s"(p)
+      : "m0");
+}
+// G[j] += a{0,1} * w (one indexed read-modify-write per file)
+__device__ __forceinline__ void bw_fma_g(int j, float a0, float a1, float w) {
+  asm volatile(
+      "s_set_gpr_idx_on %3, gpr_idx(SRC2,DST)\n\ts_nop 1\n\tv_fma_f32 v112, %0, %2, v112\n\t"
+      "v_fma_f32 v208, %1, %2, v208\n\ts_set_gpr_idx_off" ::"v"(a0),
+      "v"(a1), "v"(w), "s"(j)
+      : "m0");
+}
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_num_vgpr(TN_BW_RF_BASE))) void
+backward_rf_kernel(PopView pop, const int32_t* __restrict__ status,
+                   const int32_t* __restrict__ n_valid, const int32_t* __restrict__ order,
+                   const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ src,
+                   const int32_t* __restrict__ w_bits, const int32_t* __restrict__ edge_row,
+                   const int32_t* __restrict__ fn, const int32_t* __restrict__ bias_bits,
+                   const int32_t* __restrict__ resp_bits, const int32_t* __restrict__ io_pos,
+                   const float* __restrict__ obs, BwdArgs a) {
+  asm volatile("" ::: "v255");  // the register file counts in the allocation
+  __shared__ float slots[kRfSlots * kSlotRow];
+  __shared__ int32_t maps[2 * kWave];
+  const int g = blockIdx.x;
+  const int lane = lane_id();
+  const int I = pop.n_in, O = pop.n_out, nio = I + O;
+  const int64_t nb = uniform64(pop.node_base(g)), cb = uniform64(pop.conn_base(g)),
+                rb = uniform64(pop.rowptr_base(g));
+  const int64_t nrows = pop.node_rows(g), crows = pop.conn_rows(g);
+  const int n = n_valid[g];
+  const int n_edges = status[g] ? 0 : row_ptr[rb + n];
+  if (!rf_bwd_eligible(status[g], n, n_edges, fn + nb)) return;  // the LDS kernel's genome
+  // the program across the lanes
+  const int l_fn = lane < n ? fn[nb + lane] : 0;
+  const int l_bias = lane < n ? bias_bits[nb + lane] : 0;
+  const int l_resp = lane < n ? resp_bits[nb + lane] : 0;
+  const int l_rp = lane <= n ? row_ptr[rb + lane] : 0;
+  const int l_src = lane < n_edges ? src[cb + lane] : 0;
+  const int l_w = lane < n_edges ? w_bits[cb + lane] : 0;
+  const int l_io = lane < nio ? io_pos[(int64_t)g * nio + lane] : 0;
+  float* my = slots + lane;  // slot s of this lane at my[s * kSlotRow]
+#pragma unroll 1
+  for (int s = 0; s < kRfSlots; ++s) my[s * kSlotRow] = 0.0f;
+  float sse = 0.0f;
+  const int n_steps = (a.B + 2 * kWave - 1) / (2 * kWave);
+  for (int t = 0; t < n_steps; ++t) {
+    int bk[2];
+    bool live[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      bk[k] = t * 2 * kWave + k * kWave + lane;
+      live[k] = bk[k] < a.B;
+    }
+    const float* xg = obs + (int64_t)g * a.obs_stride;
+    // inputs (gradient rows cleared with them)
+    for (int c = 0; c < I; ++c) {
+      const int p = __builtin_amdgcn_readlane(l_io, c);
+      const float x0 = live[0] ? xg[(int64_t)bk[0] * I + c] : 0.0f;
+      const float x1 = live[1] ? xg[(int64_t)bk[1] * I + c] : 0.0f;
+      bw_set_v(p, x0, x1);
+    }
+    // forward
+    for (int p = 0; p < n; ++p) {
+      const int f = __builtin_amdgcn_readlane(l_fn, p);
+      if (f < 0) continue;
+      const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
+      float sum[2] = {0.0f, 0.0f};
+      for (int e = e0; e < e1; ++e) {
+        const int j = __builtin_amdgcn_readlane(l_src, e);
+        bw_fma_v(sum[0], sum[1], __int_as_float(__builtin_amdgcn_readlane(l_w, e)), j);
+      }
+      if (((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0) {
+        sum[0] = sum[0] / (float)(e1 - e0);
+        sum[1] = sum[1] / (float)(e1 - e0);
+      }
+      const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));
+      const float bias = __int_as_float(__builtin_amdgcn_readlane(l_bias, p));
+      // one tile at a time (the empty asm keeps the compiler from
+      // interleaving them: less register pressure in sin's reduction)
+      const float z0[1] = {fmaf(rho, sum[0], bias)}, z1[1] = {fmaf(rho, sum[1], bias)};
+      float v0[1], v1[1];
+      activate_all<1>(f & 0xff, z0, v0);
+      asm volatile("" : "+v"(v0[0]));
+      activate_all<1>(f & 0xff, z1, v1);
+      bw_set_v(p, v0[0], v1[0]);
+    }
+    // upstream gradient at the outputs
+    for (int jo = 0; jo < O; ++jo) {
+      const int pj = __builtin_amdgcn_readlane(l_io, I + jo);
+      float y[2];
+      bw_get_v(pj, y[0], y[1]);
+      float gy[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        gy[k] = 0.0f;
+        if (live[k]) {
+          const int64_t o = (int64_t)bk[k] * O + jo;
+          if (a.dY) {
+            gy[k] = a.dY[(int64_t)g * a.dY_stride + o];
+          } else {
+            const float d = y[k] - a.target[(int64_t)g * a.target_stride + o];
+            sse = fmaf(d, d, sse);
+            gy[k] = 2.0f * a.scale * d;
+          }
+        }
+      }
+      bw_fma_g(pj, gy[0], gy[1], 1.0f);
+    }
+    // reverse sweep
+    for (int p = n - 1; p >= 0; --p) {
+      const int f = __builtin_amdgcn_readlane(l_fn, p);
+      if (f < 0) continue;
+      const int act = f & 0xff;
+      const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
+      const bool mean = ((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0;
+      const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));
+      float g0, g1, v0, v1;
+      bw_get_gv(p, g0, g1, v0, v1);
+      float z[2] = {0.0f, 0.0f};
+      if (slope_needs_z(act)) {
+        float sum[2] = {0.0f, 0.0f};
+        for (int e = e0; e < e1; ++e) {
+          const int j = __builtin_amdgcn_readlane(l_src, e);
+          bw_fma_v(sum[0], sum[1], __int_as_float(__builtin_amdgcn_readlane(l_w, e)), j);
+        }
+        if (mean) {
+          sum[0] = sum[0] / (float)(e1 - e0);
+          sum[1] = sum[1] / (float)(e1 - e0);
+        }
+        const float bias = __int_as_float(__builtin_amdgcn_readlane(l_bias, p));
+        z[0] = fmaf(rho, sum[0], bias);
+        z[1] = fmaf(rho, sum[1], bias);
+      }
+      float d0 = live[0] ? g0 * act_slope(act, v0, z[0]) : 0.0f;
+      asm volatile("" : "+v"(d0));
+      const float d1 = live[1] ? g1 * act_slope(act, v1, z[1]) : 0.0f;
+      my[(kRfEdges + p) * kSlotRow] += d0 + d1;
+      float dt0 = d0 * rho, dt1 = d1 * rho;
+      if (mean) {
+        dt0 = dt0 / (float)(e1 - e0);
+        dt1 = dt1 / (float)(e1 - e0);
+      }
+      for (int e = e0; e < e1; ++e) {
+        const float old = my[e * kSlotRow];
+        const int j = __builtin_amdgcn_readlane(l_src, e);
+        float t[2];
+        bw_get_v(j, t[0], t[1]);
+        bw_fma_g(j, dt0, dt1, __int_as_float(__builtin_amdgcn_readlane(l_w, e)));
+        my[e * kSlotRow] = old + fmaf(dt1, t[1], dt0 * t[0]);
+      }
+    }
+  }
+  wave_sync();
+  // slot s (edge s, or position s - kRfEdges) summed by lane s in lane order
+  float sums[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = h * kWave + lane;
+    float acc = 0.0f;
+    if (s < kRfSlots)
+#pragma unroll 8
+      for (int b = 0; b < kWave; ++b) acc += slots[s * kSlotRow + b];
+    sums[h] = acc;
+  }
+  // write every row of the genome's blocks once: row -> edge / position maps
+  int32_t* row_edge = maps;
+  int32_t* row_pos = maps + kWave;
+  wave_sync();
+  for (int64_t r0 = 0; r0 < crows; r0 += kWave) {
+    row_edge[lane] = -1;
+    wave_sync();
+    if (lane < n_edges) {
+      const int64_t r = edge_row[cb + lane] - r0;
+      if (r >= 0 && r < kWave) row_edge[r] = lane;
+    }
+    wave_sync();
+    const int e = row_edge[lane];
+    const float dwv = __shfl(sums[0], e < 0 ? 0 : e, kWave);
+    if (r0 + lane < crows) a.dW[cb + r0 + lane] = e >= 0 ? dwv : 0.0f;
+    wave_sync();
+  }
+  for (int64_t r0 = 0; r0 < nrows; r0 += kWave) {
+    row_pos[lane] = -1;
+    wave_sync();
+    if (lane < n && l_fn >= 0) {
+      const int64_t r = order[nb + lane] - r0;
+      if (r >= 0 && r < kWave) row_pos[r] = lane;
+    }
+    wave_sync();
+    const int p = row_pos[lane];
+    // position p's sum is slot kRfEdges + p: lane p of sums[0] for p < 0,
+    // i.e. lane (kRfEdges + p) - 64 of sums[1]
+    const int sl = kRfEdges + (p < 0 ? 0 : p);
+    const float lo = __shfl(sums[0], sl & (kWave - 1), kWave);
+    const float hi = __shfl(sums[1], sl & (kWave - 1), kWave);
+    const float dbv = sl < kWave ? lo : hi;
+    if (r0 + lane < nrows) a.db[nb + r0 + lane] = p >= 0 ? dbv : 0.0f;
+    wave_sync();
+  }
+  if (a.loss) {
+    const float total = wave_sum(sse);
+    if (lane == 0) a.loss[g] = a.scale * total;
+  }
+}
+
 }  // namespace
 
 int launch_backward(const tn_population& p, const tn_transformed& t, const float* obs,
@@ -294,6 +571,13 @@ int launch_backward(const tn_population& p, const tn_transformed& t, const float
   int rc = allow_lds((const void*)backward_kernel, lds);
   if (rc != TN_OK || p.P == 0) return rc;
   BwdArgs a{obs_stride, B, dY, dY_stride, target, target_stride, scale, loss, dW, db};
+  hipLaunchKernelGGL(backward_rf_kernel, dim3(p.P), dim3(kWave), 0, stream, make_view(p),
+                     t.status, t.n_valid, t.order, t.row_ptr, t.edge_src,
+                     reinterpret_cast<const int32_t*>(t.edge_w), t.edge_row, t.pos_fn,
+                     reinterpret_cast<const int32_t*>(t.pos_bias),
+                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, obs, a);
+  rc = check_launch();
+  if (rc != TN_OK) return rc;
   hipLaunchKernelGGL(backward_kernel, dim3(p.P), dim3(kWave), lds, stream, make_view(p), t.status,
                      t.n_valid, t.order, t.row_ptr, t.edge_src,
                      reinterpret_cast<const int32_t*>(t.edge_w), t.edge_row, t.pos_fn,
