@@ -7,13 +7,11 @@
 //         bitonic-sort them by marking, flag repeated markings, and store the
 //         sorted list position-major (keysT[k][g]) so that 64 genomes' k-th
 //         genes are 64 consecutive words.
-//   pairs block = one "row" genome i x 256 "column" genomes. The row genome's
-//         genes go into an LDS hash (marking -> weight) plus its sorted list.
-//         Each lane walks its column genome's sorted list (coalesced across the
-//         wavefront), probes the hash for matches (|dw| summed in ascending
-//         marking order), counts the column genes beyond the row's largest
-//         marking, and binary-searches the row's genes beyond the column's
-//         largest marking.
+//   pairs block = up to 8 "row" genomes x 256 "column" genomes (see
+//         pair_kernel): row genes in LDS hashes, each column gene read once
+//         and probed against every row.
+#include <algorithm>
+
 #include "tn_internal.hpp"
 
 namespace tn {
@@ -40,6 +38,7 @@ struct Ws {
   long long* maxk;   // [P] largest marking, -1 when there are none
   long long* keysT;  // [C_max][P]
   float* wT;         // [C_max][P]
+  int32_t* hT;       // [C_max][P] hash of each marking (hash_mark), computed once
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -55,12 +54,15 @@ Ws carve(void* base, int P, int C) {
   w.keysT = (long long*)(p + o);
   o += align_up(sizeof(long long) * (size_t)P * C);
   w.wT = (float*)(p + o);
+  o += align_up(sizeof(float) * (size_t)P * C);
+  w.hT = (int32_t*)(p + o);
   return w;
 }
 
 size_t ws_bytes(int P, int C) {
   return align_up(sizeof(int32_t) * P) + align_up(sizeof(long long) * P) +
-         align_up(sizeof(long long) * (size_t)P * C) + align_up(sizeof(float) * (size_t)P * C);
+         align_up(sizeof(long long) * (size_t)P * C) + align_up(sizeof(float) * (size_t)P * C) +
+         align_up(sizeof(int32_t) * (size_t)P * C);
 }
 
 int next_pow2(int x) {
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(kWave) void prep_kernel(PopView pop, Ws ws, int S) 
   for (int k = lane; k < n; k += kWave) {
     ws.keysT[(int64_t)k * P + g] = key[k];
     ws.wT[(int64_t)k * P + g] = w[k];
+    ws.hT[(int64_t)k * P + g] = (int32_t)hash_mark(key[k]);
   }
   if (lane == 0) {
     ws.cnt[g] = dup ? -1 : n;
@@ -143,78 +146,116 @@ __global__ __launch_bounds__(kWave) void prep_kernel(PopView pop, Ws ws, int S) 
 }
 
 constexpr int kPairBlock = 256;
+constexpr int kMaxRows = 2;  // row genomes per block (measured best of 1, 2, 4, 8)
 
-__global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, float c1, float c2,
-                                                           float c3, float* dist, int32_t* E_out,
+// Block = up to kMaxRows "row" genomes i0 .. i0+R-1 x 256 "column" genomes.
+// Each row genome's genes go into an LDS hash (marking -> weight) plus its
+// sorted list. Each lane walks its column genome's sorted list once
+// (coalesced across the wavefront), hashes every marking once and probes all
+// R tables: matches (|dw| summed in ascending marking order per row), column
+// genes beyond each row's largest marking; then per row a binary search for
+// the row's genes beyond the column's largest marking. The column genes are
+// read from memory once per R rows.
+__global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, int C, int R,
+                                                           float c1, float c2, float c3,
+                                                           float* dist, int32_t* E_out,
                                                            int32_t* D_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  long long* hk = (long long*)smem;                                // [HC]
-  float* hw = (float*)(smem + sizeof(long long) * HC);             // [HC]
-  long long* si = (long long*)(smem + (sizeof(long long) + sizeof(float)) * HC);  // [n_i]
-  const int i = blockIdx.y;
+  // per row r: hash keys [HC], hash weights [HC], sorted list [C]
+  long long* hk_all = (long long*)smem;                                   // [R][HC]
+  long long* si_all = hk_all + (size_t)R * HC;                             // [R][C]
+  float* hw_all = (float*)(si_all + (size_t)R * C);                        // [R][HC]
+  const int i0 = blockIdx.y * R;
   const int j = blockIdx.x * kPairBlock + threadIdx.x;
-  const int ni = ws.cnt[i];
-  const long long maxi = ws.maxk[i];
-  for (int h = threadIdx.x; h < HC; h += kPairBlock) hk[h] = -1;
+  const int nr = min(R, P - i0);
+  for (int h = threadIdx.x; h < nr * HC; h += kPairBlock) hk_all[h] = -1;
   __syncthreads();
-  for (int k = threadIdx.x; k < ni; k += kPairBlock) {
-    const long long key = ws.keysT[(int64_t)k * P + i];
-    si[k] = key;
-    uint32_t h = hash_mark(key) & (uint32_t)(HC - 1);
-    while (atomicCAS((unsigned long long*)&hk[h], ~0ull, (unsigned long long)key) != ~0ull)
-      h = (h + 1) & (uint32_t)(HC - 1);
-    hw[h] = ws.wT[(int64_t)k * P + i];
+  for (int r = 0; r < nr; ++r) {
+    const int i = i0 + r;
+    const int ni = ws.cnt[i];
+    long long* hk = hk_all + (size_t)r * HC;
+    float* hw = hw_all + (size_t)r * HC;
+    long long* si = si_all + (size_t)r * C;
+    for (int k = threadIdx.x; k < ni; k += kPairBlock) {
+      const long long key = ws.keysT[(int64_t)k * P + i];
+      si[k] = key;
+      uint32_t h = (uint32_t)ws.hT[(int64_t)k * P + i] & (uint32_t)(HC - 1);
+      while (atomicCAS((unsigned long long*)&hk[h], ~0ull, (unsigned long long)key) != ~0ull)
+        h = (h + 1) & (uint32_t)(HC - 1);
+      hw[h] = ws.wT[(int64_t)k * P + i];
+    }
   }
   __syncthreads();
   if (j >= P) return;
   const int nj = ws.cnt[j];
-  const int64_t o = (int64_t)i * P + j;
-  if (ni < 0 || nj < 0) {
-    dist[o] = __builtin_nanf("");
-    if (E_out) {
-      E_out[o] = -1;
-      D_out[o] = -1;
-    }
-    return;
+  int ni[kMaxRows];
+  long long maxi[kMaxRows];
+  int M[kMaxRows], ex[kMaxRows];
+  float S[kMaxRows];
+#pragma unroll
+  for (int r = 0; r < kMaxRows; ++r) {
+    ni[r] = r < nr ? ws.cnt[i0 + r] : 0;
+    maxi[r] = r < nr ? ws.maxk[i0 + r] : -1;
+    M[r] = 0;
+    ex[r] = 0;
+    S[r] = 0.0f;
   }
-  const long long maxj = ws.maxk[j];
-  int M = 0, ex = 0;
-  float S = 0.0f;
-  for (int k = 0; k < nj; ++k) {
+  for (int k = 0; k < max(nj, 0); ++k) {
     const long long key = ws.keysT[(int64_t)k * P + j];
     const float w = ws.wT[(int64_t)k * P + j];
-    ex += key > maxi;
-    uint32_t h = hash_mark(key) & (uint32_t)(HC - 1);
-    while (true) {
-      const long long kk = hk[h];
-      if (kk == key) {
-        ++M;
-        S += fabsf(hw[h] - w);
-        break;
+    const uint32_t h0 = (uint32_t)ws.hT[(int64_t)k * P + j] & (uint32_t)(HC - 1);
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+      if (r >= nr || ni[r] < 0) continue;
+      ex[r] += key > maxi[r];
+      const long long* hk = hk_all + (size_t)r * HC;
+      uint32_t h = h0;
+      while (true) {
+        const long long kk = hk[h];
+        if (kk == key) {
+          ++M[r];
+          S[r] += fabsf(hw_all[(size_t)r * HC + h] - w);
+          break;
+        }
+        if (kk == -1) break;
+        h = (h + 1) & (uint32_t)(HC - 1);
       }
-      if (kk == -1) break;
-      h = (h + 1) & (uint32_t)(HC - 1);
     }
   }
-  // row genes beyond the column's largest marking: ni - upper_bound(si, maxj)
-  int lo = 0, hi = ni;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (si[mid] <= maxj) lo = mid + 1;
-    else hi = mid;
-  }
-  const int E = ex + (ni - lo);
-  const int D = ni + nj - 2 * M - E;
-  const int N = max(ni, nj);
-  float d = 0.0f;
-  if (N > 0) {
-    const float fN = (float)N;
-    d = c1 * (float)E / fN + c2 * (float)D / fN + c3 * (M > 0 ? S / (float)M : 0.0f);
-  }
-  dist[o] = d;
-  if (E_out) {
-    E_out[o] = E;
-    D_out[o] = D;
+  const long long maxj = ws.maxk[j];
+#pragma unroll
+  for (int r = 0; r < kMaxRows; ++r) {
+    if (r >= nr) continue;
+    const int64_t o = (int64_t)(i0 + r) * P + j;
+    if (ni[r] < 0 || nj < 0) {
+      dist[o] = __builtin_nanf("");
+      if (E_out) {
+        E_out[o] = -1;
+        D_out[o] = -1;
+      }
+      continue;
+    }
+    // row genes beyond the column's largest marking: ni - upper_bound(si, maxj)
+    const long long* si = si_all + (size_t)r * C;
+    int lo = 0, hi = ni[r];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (si[mid] <= maxj) lo = mid + 1;
+      else hi = mid;
+    }
+    const int E = ex[r] + (ni[r] - lo);
+    const int D = ni[r] + nj - 2 * M[r] - E;
+    const int N = max(ni[r], nj);
+    float d = 0.0f;
+    if (N > 0) {
+      const float fN = (float)N;
+      d = c1 * (float)E / fN + c2 * (float)D / fN + c3 * (M[r] > 0 ? S[r] / (float)M[r] : 0.0f);
+    }
+    dist[o] = d;
+    if (E_out) {
+      E_out[o] = E;
+      D_out[o] = D;
+    }
   }
 }
 
@@ -227,8 +268,11 @@ int launch_distance(const tn_population& p, float c1, float c2, float c3, void* 
   const int S = next_pow2(p.C_max);
   const size_t prep_lds = (sizeof(long long) + sizeof(float)) * (size_t)S;
   const int HC = next_pow2(2 * p.C_max);
-  const size_t pair_lds = (sizeof(long long) + sizeof(float)) * (size_t)HC +
-                          sizeof(long long) * (size_t)p.C_max;
+  const size_t per_row = (sizeof(long long) + sizeof(float)) * (size_t)HC +
+                         sizeof(long long) * (size_t)p.C_max;
+  // row genomes per block: as many as fit 64 KB of LDS (two blocks per CU), >= 1
+  const int R = (int)std::max<size_t>(1, std::min<size_t>(kMaxRows, (64 * 1024) / per_row));
+  const size_t pair_lds = per_row * R;
   int rc = allow_lds((const void*)prep_kernel, prep_lds);
   if (rc == TN_OK) rc = allow_lds((const void*)pair_kernel, pair_lds);
   if (rc != TN_OK || p.P == 0) return rc;
@@ -236,9 +280,9 @@ int launch_distance(const tn_population& p, float c1, float c2, float c3, void* 
   hipLaunchKernelGGL(prep_kernel, dim3(p.P), dim3(kWave), prep_lds, stream, make_view(p), ws, S);
   rc = check_launch();
   if (rc != TN_OK) return rc;
-  dim3 grid((p.P + kPairBlock - 1) / kPairBlock, p.P);
-  hipLaunchKernelGGL(pair_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HC, c1, c2,
-                     c3, dist, E, D);
+  dim3 grid((p.P + kPairBlock - 1) / kPairBlock, (p.P + R - 1) / R);
+  hipLaunchKernelGGL(pair_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HC,
+                     p.C_max, R, c1, c2, c3, dist, E, D);
   return check_launch();
 }
 
