@@ -37,7 +37,18 @@ struct RegArgs {
   int n_items;             // grid form: list length * n_groups; persistent: * n_tiles
   int in_phase;            // register file: tiles of inputs staged per LDS-direct round (0: chunks)
   int stage_stride;        // floats of LDS staging per wavefront
+  int n_list;              // persistent form: list length
 };
+
+// Persistent form, XCD-aware: workgroup b runs on XCD b % 8 (the round-robin
+// dispatch of MI355X's 8 XCDs); the list entries e with e % 8 == x form XCD
+// x's share, taken from counter x, so that the units of one genome run under
+// one L2 and its program is fetched from HBM once. Entry and unit of item i of
+// share x (items: entry-major, units consecutive).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int share_items(int n_list, int x, int units) {
+  return n_list > x ? ((n_list - x + kXcds - 1) / kXcds) * units : 0;
+}
 
 // Observations and outputs pass through LDS in chunks of up to kChunk
 // components per observation; a row of the chunk has an odd stride, so the
@@ -343,10 +354,10 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
   }
 }
 
-// Persistent form: the workgroup takes the next W * chunk (list entry, tile)
-// items from a counter (one atomic per grab: a single counter serialises its
-// atomics) and wavefront w runs items base + w, base + w + W, ...; list entries
-// are ordered longest first. The counter must be 0 at launch.
+// Persistent form: the workgroup takes the next W * chunk (list entry, unit)
+// items of its XCD's share from that share's counter (one atomic per grab) and
+// wavefront w runs items base + w, base + w + W, ...; list entries are ordered
+// longest first. The kXcds counters must be 0 at launch.
 template <int NB>
 __global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PARAMS) {
   extern __shared__ __align__(16) float stage_all[];
@@ -354,18 +365,20 @@ __global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PAR
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
   float* stg = stage_all + wave * kStage;
+  const int x = blockIdx.x % kXcds;
+  const int n_share = share_items(a.n_list, x, a.n_tiles);
   for (;;) {
-    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
+    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue + x, W * a.per_wave);
     __syncthreads();
     const int base = __builtin_amdgcn_readfirstlane(base_sh);  // uniform: scalar program loads
     __syncthreads();
-    if (base >= a.n_items) break;
+    if (base >= n_share) break;
     for (int c = 0; c < a.per_wave; ++c) {
       const int item = base + c * W + wave;
-      if (item >= a.n_items) break;
-      const int e = item / a.n_tiles, t = item - e * a.n_tiles;
+      if (item >= n_share) break;
+      const int le = item / a.n_tiles, t = item - le * a.n_tiles;
       int st;
-      reg_genome<NB, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+      reg_genome<NB, false>(TN_REG_ARGS, a.genomes[le * kXcds + x], t, t + 1, 1, stg, &st);
     }
   }
 }
@@ -420,18 +433,20 @@ forward_rf_queue_kernel(TN_REG_PARAMS) {
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
   float* stg = stage_all + wave * a.stage_stride;
+  const int x = blockIdx.x % kXcds;
+  const int n_share = share_items(a.n_list, x, a.n_tiles);
   for (;;) {
-    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue, W * a.per_wave);
+    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue + x, W * a.per_wave);
     __syncthreads();
     const int base = __builtin_amdgcn_readfirstlane(base_sh);
     __syncthreads();
-    if (base >= a.n_items) break;
+    if (base >= n_share) break;
     for (int c = 0; c < a.per_wave; ++c) {
       const int item = base + c * W + wave;
-      if (item >= a.n_items) break;
-      const int e = item / a.n_tiles, t = item - e * a.n_tiles;
+      if (item >= n_share) break;
+      const int le = item / a.n_tiles, t = item - le * a.n_tiles;
       int st;
-      reg_genome<R, false>(TN_REG_ARGS, a.genomes[e], t, t + 1, 1, stg, &st);
+      reg_genome<R, false>(TN_REG_ARGS, a.genomes[le * kXcds + x], t, t + 1, 1, stg, &st);
     }
   }
 }
@@ -474,6 +489,7 @@ template <int V>
 int launch_queue(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
                  const RegArgs& a, int grid, int waves, hipStream_t stream) {
   if (grid == 0) return TN_OK;
+  grid = (grid + kXcds - 1) / kXcds * kXcds;  // every XCD's share gets workgroups
   const size_t lds = sizeof(float) * (size_t)a.stage_stride * waves;
 #define TN_REG_LAUNCH(K)                                                                    \
   hipLaunchKernelGGL((K), dim3((unsigned)grid), dim3(kWave * waves), lds, stream, make_view(p), \
@@ -518,8 +534,9 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
   const int n_tiles = ((B + kWave - 1) / kWave + kt - 1) / kt;
   RegArgs a{obs_stride, B,  0, 0.0f, 0.0f, n_tiles, 1, n_tiles, rows, tile.rows_lo,
             tile.skip_above ? 1 : 0, work.genomes, work.queue, 0, dma_phase(variant, p.n_in),
-            stage_floats(variant, p.n_in)};
+            stage_floats(variant, p.n_in), n_list};
   if (work.queue) {
+    if (!work.genomes) return TN_EINVAL;  // the persistent form takes a list
     a.n_items = n_list * n_tiles;
     // items per wavefront per grab: about 4 grabs per resident workgroup
     a.per_wave = std::max(1, (int)((int64_t)a.n_items / (4LL * waves * std::max(1, work.grid))));
@@ -556,7 +573,7 @@ int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, con
   if (waves > 8) return TN_EINVAL;
   const int n_tiles = (B + kWave - 1) / kWave;
   RegArgs a{obs_stride, B,  target_stride, scale,   offset, n_tiles, 1, n_tiles, 64, -1,
-            skip_above ? 1 : 0, nullptr, nullptr, 0, 0, stage_floats(0, p.n_in)};
+            skip_above ? 1 : 0, nullptr, nullptr, 0, 0, stage_floats(0, p.n_in), p.P};
   return launch_grid<0, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
 }
 

@@ -10,7 +10,8 @@ namespace tn {
 struct FwdWork {
   const int32_t* genomes = nullptr;  // device list of genome indices (nullptr: all P, in order)
   int n_genomes = 0;                 // list length
-  int32_t* queue = nullptr;          // persistent form: device counter, 0 at launch
+  int32_t* queue = nullptr;          // persistent form: device counters, 0 at launch (8 for the
+                                     // register engine: one per XCD share; 1 for the LDS engine)
   int grid = 0;                      // persistent form: workgroups
 };
 

@@ -50,9 +50,10 @@ struct Bucket {
 };
 
 __global__ void zero_counters(int32_t* c, int n) {
-  const int i = threadIdx.x;
-  if (i < n) c[i] = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
+
+constexpr int kCountersPerBucket = 8;  // the register engine's XCD shares
 
 }  // namespace
 
@@ -132,13 +133,15 @@ int build_graph(tn_plan& pl, const float* obs, int64_t stride, float* out) {
   }
   int rc = record_hip(hipStreamBeginCapture(pl.cap, hipStreamCaptureModeThreadLocal));
   if (rc != TN_OK) return rc;
-  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, pl.cap, pl.d_counters, nb);
+  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, pl.cap, pl.d_counters,
+                     nb * kCountersPerBucket);
   rc = tn::check_launch();
   if (rc == TN_OK) rc = record_hip(hipEventRecord(pl.ev[0], pl.cap));
   for (int i = 0; i < nb && rc == TN_OK; ++i) {
     rc = record_hip(hipStreamWaitEvent(pl.side[i], pl.ev[0], 0));
     if (rc == TN_OK)
-      rc = launch_bucket(pl, pl.buckets[i], obs, stride, out, pl.d_counters + i, pl.side[i]);
+      rc = launch_bucket(pl, pl.buckets[i], obs, stride, out,
+                         pl.d_counters + i * kCountersPerBucket, pl.side[i]);
     if (rc == TN_OK) rc = record_hip(hipEventRecord(pl.ev[i + 1], pl.side[i]));
     if (rc == TN_OK) rc = record_hip(hipStreamWaitEvent(pl.cap, pl.ev[i + 1], 0));
   }
@@ -350,7 +353,8 @@ int tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t B
   const int nb = (int)pl->buckets.size();
   if (nb > 0) {
     rc = record_hip(hipMalloc(&pl->d_lists, sizeof(int32_t) * lists.size()));
-    if (rc == TN_OK) rc = record_hip(hipMalloc(&pl->d_counters, sizeof(int32_t) * nb));
+    if (rc == TN_OK)
+      rc = record_hip(hipMalloc(&pl->d_counters, sizeof(int32_t) * nb * kCountersPerBucket));
     if (rc == TN_OK)
       rc = record_hip(hipMemcpy(pl->d_lists, lists.data(), sizeof(int32_t) * lists.size(),
                                 hipMemcpyHostToDevice));
@@ -441,10 +445,11 @@ int tn_plan_forward_bucket(tn_plan* plan, int32_t i, int32_t persistent, const f
   if (!persistent) return launch_bucket(*plan, b, obs, obs_genome_stride, out, nullptr, stream);
   b.grid = persistent_grid(*plan, b);
   if (b.grid <= 0) return TN_EHIP;
-  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, stream, plan->d_counters + i, 1);
+  int32_t* counters = plan->d_counters + i * kCountersPerBucket;
+  hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, stream, counters, kCountersPerBucket);
   rc = tn::check_launch();
   if (rc != TN_OK) return rc;
-  return launch_bucket(*plan, b, obs, obs_genome_stride, out, plan->d_counters + i, stream);
+  return launch_bucket(*plan, b, obs, obs_genome_stride, out, counters, stream);
 }
 
 int tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
