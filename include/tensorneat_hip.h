@@ -265,7 +265,8 @@ int tn_forward(const tn_population* pop, const tn_transformed* tr,
                float* out, hipStream_t stream);
 
 /* How the forward pass is laid out on the chip. Two engines:
- *   TN_ENGINE_LDS  a workgroup of waves_per_genome wavefronts (1..8) evaluates
+ *   TN_ENGINE_LDS  a workgroup of waves_per_genome wavefronts (1..16 at
+ *                  obs_per_lane 1, else 1..8) evaluates
  *                  one genome on tiles of 64 * obs_per_lane observations
  *                  (obs_per_lane = 1, 2 or 4 consecutive ones per lane) with
  *                  `rows` value rows of the tile in LDS (0: N_max), splitting
@@ -371,7 +372,8 @@ int  tn_plan_create(const tn_population* pop, const tn_transformed* tr, int32_t 
 void tn_plan_destroy(tn_plan* plan);
 int  tn_plan_num_buckets(const tn_plan* plan);
 int  tn_plan_bucket(const tn_plan* plan, int32_t i, tn_bucket_info* info);
-/* Sets bucket i's tile: obs_per_lane (REG: 1; LDS: 1, 2, 4), waves (1..8). */
+/* Sets bucket i's tile: obs_per_lane (REG: 1; LDS: 1, 2, 4), waves (REG: 1..8; LDS:
+ * 1..16 at one observation per lane, else 1..8). */
 int  tn_plan_set_tile(tn_plan* plan, int32_t i, int32_t obs_per_lane, int32_t waves);
 int  tn_plan_forward(tn_plan* plan, const float* obs, int64_t obs_genome_stride, float* out,
                      hipStream_t stream);

@@ -199,7 +199,8 @@ int tn_forward_tiled(const tn_population* pop, const tn_transformed* tr, const f
   const int engine = tile ? tile->engine : TN_ENGINE_AUTO;
   if (tile) {
     const int K = tile->obs_per_lane, W = tile->waves_per_genome, R = tile->rows;
-    if (W < 0 || W > 8 || R < 0) return TN_EINVAL;
+    if (W < 0 || W > (engine == TN_ENGINE_LDS ? tn::lds_max_waves(K) : 8) || R < 0)
+      return TN_EINVAL;
     if (engine == TN_ENGINE_LDS && K != 0 && K != 1 && K != 2 && K != 4) return TN_EINVAL;
     if (engine == TN_ENGINE_REG &&
         ((K != 0 && K != 1) ||

@@ -285,7 +285,7 @@ __device__ __forceinline__ void lds_genome(
 
 // One workgroup per (genome, group of consecutive tiles).
 template <int K, bool kLoss, bool kProgLds>
-__global__ __launch_bounds__(kWave * 8) void forward_kernel(TN_FWD_PARAMS) {
+__global__ __launch_bounds__(kWave * lds_max_waves(K)) void forward_kernel(TN_FWD_PARAMS) {
   int item, t_begin, t_end;
   if (kLoss) {
     item = blockIdx.x;
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kWave * 8) void forward_kernel(TN_FWD_PARAMS) {
 // (longest first) from a counter, one atomic per grab, until the list is
 // exhausted; the counter must be 0 at launch.
 template <int K, bool kProgLds>
-__global__ __launch_bounds__(kWave * 8) void forward_queue_kernel(TN_FWD_PARAMS) {
+__global__ __launch_bounds__(kWave * lds_max_waves(K)) void forward_queue_kernel(TN_FWD_PARAMS) {
   __shared__ int item_sh;
   for (;;) {
     if (threadIdx.x == 0) item_sh = atomicAdd(a.queue, a.per_wg);
@@ -430,7 +430,7 @@ int launch_forward(const tn_population& p, const tn_transformed& t, const float*
   const int K = tile.K == 0 ? 1 : tile.K;
   const int waves = tile.waves <= 0 ? 4 : tile.waves;
   const int rows = tile.rows <= 0 || tile.rows > p.N_max ? p.N_max : tile.rows;
-  if (waves > 8) return TN_EINVAL;
+  if (waves > lds_max_waves(K)) return TN_EINVAL;
   const int n_list = work.genomes ? work.n_genomes : p.P;
   const int ktile = kWave * K;
   const int n_tiles = (B + ktile - 1) / ktile;

@@ -28,9 +28,12 @@ struct RegTile {
 };
 
 // Level-parallel LDS engine (forward.hip).
+// Wavefronts per workgroup it allows: 16 at one observation per lane (the
+// kernel then fits 128 registers, four wavefronts per SIMD), else 8.
+constexpr int lds_max_waves(int K) { return K <= 1 ? 16 : 8; }
 struct LdsTile {
   int K = 1;          // observations per lane (1, 2, 4)
-  int waves = 4;      // wavefronts per workgroup (1..8)
+  int waves = 4;      // wavefronts per workgroup (1..lds_max_waves(K))
   int rows = 0;       // value rows per tile (0: N_max)
   int skip_le = -1;   // genomes with prog_rows <= skip_le are skipped
 };

@@ -199,7 +199,7 @@ std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
     if (!eq) continue;
     int K = 0, W = 0;
     if (std::sscanf(eq + 3, "%d %d", &K, &W) != 2) continue;
-    if ((K != 1 && K != 2 && K != 4) || W < 1 || W > 8) continue;
+    if ((K != 1 && K != 2 && K != 4) || W < 1 || W > tn::lds_max_waves(K)) continue;
     m[std::string(line, eq)] = {K, W};
   }
   std::fclose(f);
@@ -220,7 +220,7 @@ void apply_cache(tn_plan& pl, const char* path) {
   for (Bucket& b : pl.buckets) {
     const auto it = m.find(cache_key(pl, b));
     if (it == m.end()) continue;
-    if (b.engine == TN_ENGINE_REG && it->second.first != 1) continue;
+    if (b.engine == TN_ENGINE_REG && (it->second.first != 1 || it->second.second > 8)) continue;
     if (b.engine == TN_ENGINE_LDS && tn::lds_tile_bytes(pl.pop, it->second.first, b.max_rows) == 0)
       continue;
     b.K = it->second.first;
@@ -399,8 +399,9 @@ int tn_plan_bucket(const tn_plan* plan, int32_t i, tn_bucket_info* info) {
 }
 
 int tn_plan_set_tile(tn_plan* plan, int32_t i, int32_t obs_per_lane, int32_t waves) {
-  if (!plan || i < 0 || i >= (int)plan->buckets.size() || waves < 1 || waves > 8) return TN_EINVAL;
+  if (!plan || i < 0 || i >= (int)plan->buckets.size() || waves < 1) return TN_EINVAL;
   Bucket& b = plan->buckets[i];
+  if (waves > (b.engine == TN_ENGINE_REG ? 8 : tn::lds_max_waves(obs_per_lane))) return TN_EINVAL;
   if (b.engine == TN_ENGINE_REG ? obs_per_lane != 1
                                 : (obs_per_lane != 1 && obs_per_lane != 2 && obs_per_lane != 4))
     return TN_EINVAL;
@@ -463,12 +464,13 @@ int tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, flo
   for (size_t i = 0; i < plan->buckets.size() && rc == TN_OK; ++i) {
     Bucket& b = plan->buckets[i];
     std::vector<std::pair<int, int>> cand;
-    for (int W : {1, 2, 4, 8}) {
+    for (int W : {1, 2, 4, 8, 16}) {
       if (b.engine == TN_ENGINE_REG) {
-        cand.push_back({1, W});
+        if (W <= 8) cand.push_back({1, W});
       } else {
         for (int K : {1, 2, 4})
-          if (tn::lds_tile_bytes(plan->pop, K, b.max_rows) > 0) cand.push_back({K, W});
+          if (W <= tn::lds_max_waves(K) && tn::lds_tile_bytes(plan->pop, K, b.max_rows) > 0)
+            cand.push_back({K, W});
       }
     }
     float best = INFINITY;

@@ -113,6 +113,35 @@ def test_all_activations_aggregations_and_response(B):
     check(pop, obs, Y)
 
 
+@pytest.mark.parametrize("K,W", [(1, 1), (1, 3), (2, 3), (4, 2), (1, 16)])
+def test_lds_engine_wide_nodes_every_aggregation(K, W):
+    """The LDS engine on dense random DAGs (many nodes with more than six
+    in-edges, through the four-at-a-time in-edge loop and its remainder, some
+    with none) with every activation, aggregation and random responses, on 150
+    observations (a ragged last tile), against the oracle. Three wavefronts
+    split the levels unevenly; sixteen is the largest workgroup (one
+    observation per lane)."""
+    import paper_2504_08339_amd as tn
+    rng = np.random.default_rng(21)
+    pop = synth.random_dag_population(40, 5, 3, rng, h_lo=4, h_hi=60, c_lo=5.0, c_hi=9.0,
+                                      c_cap=400, disable_p=0.1)
+    valid = pop.node_key >= 0
+    pop.node_act[valid] = rng.integers(0, 7, size=int(valid.sum()))
+    pop.node_agg[valid] = rng.integers(0, 6, size=int(valid.sum()))
+    pop.node_resp[valid] = rng.uniform(-1.5, 1.5, size=int(valid.sum())).astype(np.float32)
+    obs = rng.uniform(-1.0, 1.0, size=(40, 150, 5)).astype(np.float32)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    wide = 0
+    for g in range(pop.P):
+        c = pop.conn_rows(g)
+        wide = max(wide, int(np.bincount(c["out"][c["en"] > 0]).max()))
+    assert wide > 6
+    Y = host(tn.forward(dp, tr, tensor(obs), engine=tn.TN_ENGINE_LDS, obs_per_lane=K,
+                        waves_per_genome=W))
+    check(pop, obs, Y)
+
+
 def test_shared_observations_and_single_row():
     pop = synth.control_population(P=30)
     X = synth.normal_obs(1, 65, 17, 5)[0]
@@ -186,7 +215,7 @@ def test_mse_loss_matches_oracle():
         assert abs(loss[g] - ref) <= 1e-5 * abs(ref) + 1e-7
 
 
-@pytest.mark.parametrize("K,W", [(1, 1), (1, 4), (2, 4), (4, 2), (2, 8)])
+@pytest.mark.parametrize("K,W", [(1, 1), (1, 4), (2, 4), (4, 2), (2, 8), (1, 16)])
 def test_lds_tile_shapes_and_tight_rows_bitwise(K, W):
     """Every LDS tile shape, with rows sized to the population's largest n_rows,
     gives the same bits as the default launch; too few rows gives NaN."""

@@ -75,7 +75,12 @@ def test_shared_observations_and_tile_changes():
     plan = tn.Plan(dp, tr, 70)
     ref = _bits(tn.forward(dp, tr, xt))
     for i, b in enumerate(plan.buckets()):
-        for K, W in ((1, 1), (1, 8)) if b["engine"] == tn.TN_ENGINE_REG else ((2, 2), (4, 1), (1, 8)):
+        # sixteen wavefronts: LDS engine at one observation per lane only
+        bad = (1, 16) if b["engine"] == tn.TN_ENGINE_REG else (2, 16)
+        with pytest.raises(tn.TNError):
+            plan.set_tile(i, *bad)
+        for K, W in ((1, 1), (1, 8)) if b["engine"] == tn.TN_ENGINE_REG else ((2, 2), (4, 1), (1, 8),
+                                                                            (1, 16)):
             try:
                 plan.set_tile(i, K, W)
             except tn.TNError:
