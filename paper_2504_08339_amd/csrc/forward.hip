@@ -136,7 +136,7 @@ __device__ __forceinline__ void lds_genome(
       const int n_edges = row_ptr[rb + n];
       for (int e = threadIdx.x; e < n_edges; e += T) {
         EdgeRec q;
-        q.src = pos_row[nb + src[cb + e]];
+        q.src = pos_row[nb + src[cb + e]] * (int)(sizeof(float) * (kWave + 1) * K);
         q.w = __int_as_float(w_bits[cb + e]);
         edges[e] = q;
       }
@@ -144,7 +144,7 @@ __device__ __forceinline__ void lds_genome(
   }
   __syncthreads();
   const int n_lvl = st ? 0 : n_lvl_sh;
-  LdsProg lp{recs, edges};
+  LdsProgT<true> lp{recs, edges};
   GlobalProg gp{row_ptr + rb, fn + nb,     bias_bits + nb, resp_bits + nb,
                 src + cb,    w_bits + cb, pos_row + nb};
 

@@ -142,18 +142,36 @@ __host__ __device__ __forceinline__ int32_t fn_with_row(int32_t fn, int32_t row)
   return fn < 0 ? fn : ((fn & 0xffff) | (row << 16));
 }
 
-// Program staged in LDS (one copy per workgroup).
-struct LdsProg {
+// Program staged in LDS (one copy per workgroup). A record is read with one
+// 16-byte load. kSrcBytes: the in-edge records hold the byte offset of the
+// source row (row * kRow * 4) instead of its index, which saves a 32-bit
+// multiply per in-edge.
+template <bool kBytes>
+struct LdsProgT {
+  static constexpr bool kSrcBytes = kBytes;
   const NodeRec* recs;
   const EdgeRec* edges;
-  __device__ __forceinline__ NodeRec node(int p) const { return recs[p]; }
+  __device__ __forceinline__ NodeRec node(int p) const {
+    const int4 q = reinterpret_cast<const int4*>(recs)[p];
+    NodeRec r;
+    r.erange = q.x;
+    r.fn = q.y;
+    r.bias = __int_as_float(q.z);
+    r.resp = __int_as_float(q.w);
+    // all four words in registers here: the read is not split around the
+    // input-position test that follows
+    asm volatile("" : "+v"(r.erange), "+v"(r.fn), "+v"(r.bias), "+v"(r.resp));
+    return r;
+  }
   __device__ __forceinline__ EdgeRec edge(int e) const { return edges[e]; }
 };
+using LdsProg = LdsProgT<false>;
 
 // Program read straight from the transformed arrays in global memory. The
 // float arrays are read through int32 views, so that the kernel's float stores
 // cannot alias them and the loads stay scalar.
 struct GlobalProg {
+  static constexpr bool kSrcBytes = false;
   const int32_t* rp;
   const int32_t* fn;
   const int32_t* bias;
@@ -181,6 +199,15 @@ struct GlobalProg {
 // floats sit at mine + row * kRow (value rows come from the program). Inputs
 // are skipped (their rows hold the observation). Sum aggregation accumulates
 // in ascending in-edge order with fused multiply-add.
+// This lane's floats of the source row of in-edge record q.
+template <int kRow, class Prog>
+__device__ __forceinline__ const float* src_row(const float* mine, const EdgeRec& q) {
+  if constexpr (Prog::kSrcBytes)
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(mine) + q.src);
+  else
+    return mine + q.src * kRow;
+}
+
 template <int K, int kRow, class Prog>
 __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) {
   const NodeRec rec = prog.node(p);
@@ -198,10 +225,10 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
       const EdgeRec q0 = prog.edge(e), q1 = prog.edge(e + 1), q2 = prog.edge(e + 2),
                     q3 = prog.edge(e + 3);
       Vec<K> x0, x1, x2, x3;
-      x0.load(mine + q0.src * kRow);
-      x1.load(mine + q1.src * kRow);
-      x2.load(mine + q2.src * kRow);
-      x3.load(mine + q3.src * kRow);
+      x0.load(src_row<kRow, Prog>(mine, q0));
+      x1.load(src_row<kRow, Prog>(mine, q1));
+      x2.load(src_row<kRow, Prog>(mine, q2));
+      x3.load(src_row<kRow, Prog>(mine, q3));
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         s[k] = fmaf(q0.w, x0.x[k], s[k]);
@@ -213,7 +240,7 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
     for (; e < e1; ++e) {
       const EdgeRec q = prog.edge(e);
       Vec<K> x;
-      x.load(mine + q.src * kRow);
+      x.load(src_row<kRow, Prog>(mine, q));
 #pragma unroll
       for (int k = 0; k < K; ++k) s[k] = fmaf(q.w, x.x[k], s[k]);
     }
@@ -224,14 +251,14 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
     {
       const EdgeRec q = prog.edge(e0);
       Vec<K> x;
-      x.load(mine + q.src * kRow);
+      x.load(src_row<kRow, Prog>(mine, q));
 #pragma unroll
       for (int k = 0; k < K; ++k) s[k] = q.w * x.x[k];
     }
     for (int e = e0 + 1; e < e1; ++e) {
       const EdgeRec q = prog.edge(e);
       Vec<K> x;
-      x.load(mine + q.src * kRow);
+      x.load(src_row<kRow, Prog>(mine, q));
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const float t = q.w * x.x[k];
