@@ -351,11 +351,12 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
  * Both write out [P][B][n_out] for observations laid out as in tn_forward
  * (obs_genome_stride 0 = shared), bitwise equal to tn_forward's outputs.
  *
- * tn_plan_tune times every tile candidate of every bucket with plain
- * launches (register buckets: 1, 2, 4, 8 wavefronts per workgroup; LDS
- * buckets: 1, 2, 4 observations per lane x 1, 2, 4, 8 wavefronts), keeps the
- * fastest, and (tune_cache != NULL) merges the choices into the cache file. It
- * writes `out` while timing and synchronises `stream`.
+ * tn_plan_tune times every tile candidate of every bucket in the persistent
+ * form tn_plan_forward's graph runs (best of five launches after a warm-up;
+ * register buckets: 1, 2, 4, 8 wavefronts per workgroup; LDS buckets: 1, 2, 4
+ * observations per lane x 1, 2, 4, 8 wavefronts, and 16 at one observation
+ * per lane), keeps the fastest, and (tune_cache != NULL) merges the choices
+ * into the cache file. It writes `out` while timing and synchronises `stream`.
  */
 typedef struct tn_plan tn_plan;
 

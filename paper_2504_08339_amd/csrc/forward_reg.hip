@@ -213,6 +213,34 @@ __device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
   }
   walk_records<R>(rec, pe, nn, lane);
   float sse = 0.0f;
+  if constexpr (!kLoss && K == 1) {
+    // one tile: outputs straight from the register file, lane l writing the O
+    // values of its observation four at a time when O is a multiple of 4 and
+    // the rows are 16-byte aligned (the stores of one group of four outputs
+    // together cover the tile's rows); with several tiles per wavefront the
+    // LDS transpose below is faster
+    if (!yg) return 0.0f;
+    const bool vec = (O & 3) == 0 && (reinterpret_cast<uintptr_t>(yg) & 15) == 0;
+    for (int c0 = 0; c0 < O; c0 += vec ? 4 : 1) {
+      float x[4][1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u > 0 && !vec) break;
+        const int c = c0 + u;
+        const int orow = c < kChunk ? __builtin_amdgcn_readlane(orow_first, c)
+                                    : __builtin_amdgcn_readfirstlane(prog_row(pn, out_pos[c]));
+        rfk_get<R>(orow, x[u]);
+      }
+      if (lane < nbat[0]) {
+        float* dst = yg + (int64_t)(b0 + lane) * O + c0;
+        if (vec)
+          *reinterpret_cast<float4*>(dst) = make_float4(x[0][0], x[1][0], x[2][0], x[3][0]);
+        else
+          *dst = x[0][0];
+      }
+    }
+    return 0.0f;
+  }
   for (int c0 = 0; c0 < O; c0 += kChunk) {
     const int ch = min(kChunk, O - c0);
     const int sr = ch | 1;

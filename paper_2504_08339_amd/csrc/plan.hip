@@ -478,10 +478,20 @@ int tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, flo
     for (const auto& c : cand) {
       b.K = c.first;
       b.waves = c.second;
+      // the persistent form, as the graph runs it (grid sized for this tile)
+      b.grid = persistent_grid(*plan, b);
+      if (b.grid <= 0) {
+        rc = TN_EHIP;
+        break;
+      }
+      int32_t* counters = plan->d_counters + i * kCountersPerBucket;
       float ms = INFINITY;
-      for (int rep = 0; rep < 4 && rc == TN_OK; ++rep) {  // the first run warms up
-        rc = record_hip(hipEventRecord(e0, stream));
-        if (rc == TN_OK) rc = launch_bucket(*plan, b, obs, obs_genome_stride, out, nullptr, stream);
+      for (int rep = 0; rep < 6 && rc == TN_OK; ++rep) {  // the first run warms up
+        hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, stream, counters,
+                           kCountersPerBucket);
+        rc = tn::check_launch();
+        if (rc == TN_OK) rc = record_hip(hipEventRecord(e0, stream));
+        if (rc == TN_OK) rc = launch_bucket(*plan, b, obs, obs_genome_stride, out, counters, stream);
         if (rc == TN_OK) rc = record_hip(hipEventRecord(e1, stream));
         if (rc == TN_OK) rc = record_hip(hipEventSynchronize(e1));
         float t = 0.0f;
@@ -496,6 +506,7 @@ int tn_plan_tune(tn_plan* plan, const float* obs, int64_t obs_genome_stride, flo
     }
     b.K = pick.first;
     b.waves = pick.second;
+    b.grid = persistent_grid(*plan, b);
     cache[cache_key(*plan, b)] = pick;
   }
   if (e0) (void)hipEventDestroy(e0);
