@@ -60,7 +60,9 @@ constexpr int stage_tiles(int V) { return V >= 32 ? rf_tiles(V) : 1; }
 
 // The register-file form stages a unit's observations with LDS-direct loads
 // (global_load_lds: memory to LDS without passing through registers, so a
-// whole round is in flight at once and waited for once), in rounds of as many
+// whole round is in flight at once and waited for once; 16 bytes per lane
+// when the source is aligned, which measured several times faster per byte
+// than one float per lane), in rounds of as many
 // of the unit's tiles as fit this many bytes per wavefront (two wavefronts per
 // SIMD then still fit the compute unit's LDS), one tile per round at least.
 constexpr int kDmaBytes = 20 * 1024;
@@ -199,7 +201,22 @@ __device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
       const int nobs = max(0, min(in_phase * kWave, B - b0 - f0 * kWave));
       const int total = nobs * I;
       const float* src = xg + (int64_t)(b0 + f0 * kWave) * I;
-      for (int j = 0; j < total; j += kWave)
+      // 16 bytes per lane (global_load_lds_dwordx4: lane i's four floats land
+      // at M0 + 16 i) while the source is 16-byte aligned, one float per lane
+      // for the rest
+      int j = 0;
+      if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+        const int full = total & ~(4 * kWave - 1);
+        const int voff = lane * 16;
+        for (; j < full; j += 4 * kWave) {
+          const uint32_t at = __builtin_amdgcn_readfirstlane(
+              (uint32_t)reinterpret_cast<uintptr_t>(stg + j));
+          asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff),
+                       "s"(src + j), "s"(at)
+                       : "memory", "m0");
+        }
+      }
+      for (; j < total; j += kWave)
         if (j + lane < total) __builtin_amdgcn_global_load_lds(src + j + lane, stg + j, 4, 0, 0);
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       for (int c = 0; c < I; ++c) {

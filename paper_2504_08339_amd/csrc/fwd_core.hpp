@@ -111,8 +111,19 @@ __device__ __forceinline__ void activate_all(int act, const float (&z)[K], float
       for (int k = 0; k < K; ++k) v[k] = fmaxf(z[k], 0.0f);
       break;
     case TN_ACT_SIN:
+      // one value at a time: the large-argument reduction of sinf needs
+      // many registers, and K of them interleaved would not fit beside an
+      // explicit register file
+    {
+      float zz[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = sinf(z[k]);
+      for (int k = 0; k < K; ++k) zz[k] = z[k];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        v[k] = sinf(zz[k]);
+        if (k + 1 < K) asm volatile("" : "+v"(v[k]), "+v"(zz[(k + 1) % K]));
+      }
+    }
       break;
     case TN_ACT_GAUSSIAN:
 #pragma unroll
