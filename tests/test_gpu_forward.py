@@ -266,6 +266,33 @@ def test_register_engine_bitwise_and_row_limit(W, rows):
         assert np.isnan(y[~fit]).all()
 
 
+@pytest.mark.parametrize("rows", [50, 100, 200])
+def test_register_engine_misaligned_buffers_bitwise(rows):
+    """Observations and outputs one float off a 16-byte boundary (views into
+    larger buffers): the register engine then stages one float per lane and
+    stores outputs one at a time, with the same bits as from aligned buffers
+    (16 bytes per lane, four outputs per store)."""
+    import paper_2504_08339_amd as tn
+    pop = synth.batching_population(P=120)
+    obs = synth.normal_obs(pop.P, 300, pop.n_in, 13)
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    xt = tensor(obs)
+    ref = host(tn.forward(dp, tr, xt, engine=tn.TN_ENGINE_REG, rows=rows, waves_per_genome=4))
+    big = torch.zeros(obs.size + 1, dtype=torch.float32, device="cuda")
+    xo = big[1:].view(obs.shape)
+    xo.copy_(xt)
+    assert xo.data_ptr() % 16 == 4
+    ybig = torch.full((pop.P * 300 * pop.n_out + 1,), 7.0, dtype=torch.float32, device="cuda")
+    yo = ybig[1:].view(pop.P, 300, pop.n_out)
+    tn.forward(dp, tr, xo, out=yo, engine=tn.TN_ENGINE_REG, rows=rows, waves_per_genome=4)
+    y = host(yo)
+    fit = host(tr.prog_rows)[:pop.P] <= rows
+    assert fit.sum() > 10
+    assert np.array_equal(y[fit].view(np.uint32), ref[fit].view(np.uint32))
+    assert float(host(ybig[:1])[0]) == 7.0
+
+
 @pytest.mark.parametrize("rows", [50, 100])
 def test_register_file_tiles_agree_bitwise(rows):
     """The tiles a wavefront holds in one register file (four at 50 rows, two
