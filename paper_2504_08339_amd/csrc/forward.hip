@@ -106,21 +106,19 @@ __device__ __forceinline__ void lds_genome(
   const int n = n_valid[g];
   const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
 
-  // stage: level starts (wavefront 0), io positions and the program (all)
+  // stage: level starts, io positions and the program, every thread a share.
+  // Levels are the Kahn rounds 0, 1, ..., each non-empty, and positions are
+  // in level order, so the start of level L is the one position p with
+  // level L whose predecessor has a lower level: one independent pass.
   if (!st) {
-    if (wave == 0) {
-      int cnt = 0;
-      for (int base = 0; base < n; base += kWave) {
-        const int p = base + lane;
-        const bool start = p < n && (p == 0 || level[nb + p] != level[nb + p - 1]);
-        const uint64_t m = __ballot(start);
-        if (start) lvl[cnt + mbcnt(m)] = p;
-        cnt += __popcll(m);
-      }
-      if (lane == 0) {
-        lvl[cnt] = n;
-        n_lvl_sh = cnt;
-      }
+    for (int p = threadIdx.x; p < n; p += T) {
+      const int lv = level[nb + p];
+      if (p == 0 || level[nb + p - 1] != lv) lvl[lv] = p;
+    }
+    if (threadIdx.x == 0) {
+      const int cnt = n > 0 ? level[nb + n - 1] + 1 : 0;
+      lvl[cnt] = n;
+      n_lvl_sh = cnt;
     }
     for (int k = threadIdx.x; k < nio; k += T)
       io_l[k] = pos_row[nb + io_pos[(int64_t)g * nio + k]];
