@@ -106,6 +106,24 @@ __device__ __forceinline__ void lds_genome(
   const int n = n_valid[g];
   const int64_t nb = pop.node_base(g), cb = pop.conn_base(g), rb = pop.rowptr_base(g);
 
+  constexpr int kMaxIn = K == 1 ? 8 : 16, kMaxOut = K == 1 ? 4 : 8;
+  const int n_in_el = kTile * I, n_out_el = kTile * O;
+  const int J_in = (n_in_el + T - 1) / T, J_out = (n_out_el + T - 1) / T;
+  const bool fast_in = J_in <= kMaxIn, fast_out = J_out <= kMaxOut;
+  float sse = 0.0f;
+  // Observations of the next full tile are loaded into registers while the
+  // current tile is evaluated (one tile of lookahead); the first tile's are
+  // requested before the program is staged.
+  float pre[kMaxIn];
+  auto load_full = [&](int tt) {
+    const float* xq = obs + (int64_t)g * a.obs_stride + (int64_t)tt * kTile * I;
+#pragma unroll
+    for (int j = 0; j < kMaxIn; ++j)
+      if (j < J_in) pre[j] = xq[threadIdx.x + j * T < n_in_el ? threadIdx.x + j * T : 0];
+  };
+  auto is_full = [&](int tt) { return tt < t_end && min(kTile, a.B - tt * kTile) == kTile; };
+  if (!st && fast_in && I > 0 && is_full(t_begin)) load_full(t_begin);
+
   // stage: level starts, io positions and the program, every thread a share.
   // Levels are the Kahn rounds 0, 1, ..., each non-empty, and positions are
   // in level order, so the start of level L is the one position p with
@@ -131,12 +149,18 @@ __device__ __forceinline__ void lds_genome(
         r.resp = __int_as_float(resp_bits[nb + p]);
         recs[p] = r;
       }
+      // two in-edges per thread and step, both sources' row loads in flight
+      // together
       const int n_edges = row_ptr[rb + n];
-      for (int e = threadIdx.x; e < n_edges; e += T) {
-        EdgeRec q;
-        q.src = pos_row[nb + src[cb + e]] * (int)(sizeof(float) * (kWave + 1) * K);
-        q.w = __int_as_float(w_bits[cb + e]);
-        edges[e] = q;
+      constexpr int kRowBytes = (int)(sizeof(float) * (kWave + 1) * K);
+      for (int e = threadIdx.x; e < n_edges; e += 2 * T) {
+        const int e2 = e + T;
+        const bool two = e2 < n_edges;
+        const int s1 = src[cb + e], s2 = two ? src[cb + e2] : 0;
+        const int w1 = w_bits[cb + e], w2 = two ? w_bits[cb + e2] : 0;
+        const int r1 = pos_row[nb + s1], r2 = two ? pos_row[nb + s2] : 0;
+        edges[e] = EdgeRec{r1 * kRowBytes, __int_as_float(w1)};
+        if (two) edges[e2] = EdgeRec{r2 * kRowBytes, __int_as_float(w2)};
       }
     }
   }
@@ -152,10 +176,6 @@ __device__ __forceinline__ void lds_genome(
   // Offsets of this thread's elements in a full tile, computed once: input
   // element i = tid + j*T (observation b, component c) goes to row io[c],
   // column b; output element i = tid + j*T comes from row io[I + c].
-  constexpr int kMaxIn = K == 1 ? 8 : 16, kMaxOut = K == 1 ? 4 : 8;
-  const int n_in_el = kTile * I, n_out_el = kTile * O;
-  const int J_in = (n_in_el + T - 1) / T, J_out = (n_out_el + T - 1) / T;
-  const bool fast_in = J_in <= kMaxIn, fast_out = J_out <= kMaxOut;
   int in_off[kMaxIn], out_off[kMaxOut];
   if (!st) {
     DivWalk di(threadIdx.x, I > 0 ? I : 1, T);
@@ -172,18 +192,6 @@ __device__ __forceinline__ void lds_genome(
     }
   }
 
-  float sse = 0.0f;
-  // Observations of the next full tile are loaded into registers while the
-  // current tile is evaluated (one tile of lookahead).
-  float pre[kMaxIn];
-  auto load_full = [&](int tt) {
-    const float* xq = obs + (int64_t)g * a.obs_stride + (int64_t)tt * kTile * I;
-#pragma unroll
-    for (int j = 0; j < kMaxIn; ++j)
-      if (j < J_in) pre[j] = xq[in_off[j] >= 0 ? threadIdx.x + j * T : 0];
-  };
-  auto is_full = [&](int tt) { return tt < t_end && min(kTile, a.B - tt * kTile) == kTile; };
-  if (!st && fast_in && I > 0 && is_full(t_begin)) load_full(t_begin);
   for (int t = t_begin; t < t_end; ++t) {
     const int b0 = t * kTile;
     const int nbat = min(kTile, a.B - b0);
