@@ -433,8 +433,15 @@ __device__ __forceinline__ float cppn_slope(int act, float v, float z) {
 // slot is reduced over the wavefront in a fixed order and written to this
 // wavefront's slot of `part`.
 // Sum and mean aggregation only (the CPPN's); other genomes get NaN.
+// The kernel is compiled for two slot counts and both forms are launched:
+// KE = 48 in-edge slots (80 per lane with the node slots: 20 KB per
+// wavefront, so eight wavefronts fit a compute unit's LDS, as many as its
+// registers allow) takes the genomes with at most 48 in-edges, KE = 64 the
+// others and writes the NaN partials of the genomes no form takes.
 constexpr int kCppnWaves = 2, kCppnUnitsPerWave = 32, kCppnUnit = 2 * kWave;
+constexpr int kCppnCompactEdges = 48;
 
+template <int KE>
 __global__ __launch_bounds__(kWave * kCppnWaves) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
 cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
                      const int32_t* __restrict__ n_valid, const int32_t* __restrict__ row_ptr,
@@ -444,14 +451,15 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
                      SubGeom sg, int n_chunks, const float* __restrict__ dw1t,
                      const float* __restrict__ dw2t, float* __restrict__ part) {
   adj_reserve();
-  __shared__ float acc_all[kCppnWaves * kCppnPart * kWave];
+  constexpr int kSlots = KE + kCppnNodes;  // LDS sums per lane: in-edges, then positions
+  __shared__ float acc_all[kCppnWaves * kSlots * kWave];
   const int lane = lane_id();
   const int wave = wave_id();
   const int W = blockDim.x / kWave;
   const int g = blockIdx.x / n_chunks;
   const int chunk = blockIdx.x - g * n_chunks;
   float* out = part + ((int64_t)g * n_chunks * W + (int64_t)chunk * W + wave) * kCppnPart;
-  float* acc = acc_all + wave * kCppnPart * kWave + lane;  // slot i at acc[i * kWave]
+  float* acc = acc_all + wave * kSlots * kWave + lane;  // slot i at acc[i * kWave]
   const int n = n_valid[g];
   const int64_t nb = uniform64(pop.node_base(g)), cb = uniform64(pop.conn_base(g)),
                 rb = uniform64(pop.rowptr_base(g));
@@ -466,10 +474,12 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
     if (f >= 0 && agg != TN_AGG_SUM && agg != TN_AGG_MEAN) ok = false;
   }
   if (!ok) {
-    for (int i = lane; i < kCppnPart; i += kWave) out[i] = __builtin_nanf("");
+    if (KE == kCppnEdges)
+      for (int i = lane; i < kCppnPart; i += kWave) out[i] = __builtin_nanf("");
     return;
   }
-  for (int i = 0; i < kCppnPart; ++i) acc[i * kWave] = 0.0f;
+  if ((n_edges <= kCppnCompactEdges) != (KE == kCppnCompactEdges)) return;  // the other form's
+  for (int i = 0; i < kSlots; ++i) acc[i * kWave] = 0.0f;
   // the genome's program across the wavefront, read once: lane p holds
   // position p's function word, bias, response and first in-edge (lane n the
   // end of the last), lane e edge e's source position and weight; the sweeps
@@ -551,7 +561,7 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
       adj_get_gvz(p, g0, g1, v0, v1, z0, z1);
       const int act = f & 0xff;
       const float d0 = g0 * cppn_slope(act, v0, z0), d1 = g1 * cppn_slope(act, v1, z1);
-      acc[(kCppnEdges + p) * kWave] += d0 + d1;
+      acc[(KE + p) * kWave] += d0 + d1;
       const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
       const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));
       float dt0 = d0 * rho, dt1 = d1 * rho;
@@ -586,10 +596,11 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
       }
     }
   }
-  // one reduction over the wavefront per sum, fixed order
-  for (int i = 0; i < kCppnPart; ++i) {
+  // one reduction over the wavefront per sum, fixed order; partial slot
+  // layout: in-edge e at e, position p at kCppnEdges + p
+  for (int i = 0; i < kSlots; ++i) {
     const float t = wave_sum(acc[i * kWave]);
-    if (lane == 0) out[i] = t;
+    if (lane == 0) out[i < KE ? i : kCppnEdges + (i - KE)] = t;
   }
 }
 
@@ -764,14 +775,19 @@ int launch_cppn_backward(const tn_population& p, const tn_transformed& t, const 
   if (grid == 0) return TN_OK;
   if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
   float* part = static_cast<float*>(workspace);
-  hipLaunchKernelGGL(cppn_backward_kernel, dim3((unsigned)grid), dim3(kWave * kCppnWaves), 0,
-                     stream, make_view(p), t.status, t.n_valid, t.row_ptr, t.edge_src,
-                     reinterpret_cast<const int32_t*>(t.edge_w), t.pos_fn,
-                     reinterpret_cast<const int32_t*>(t.pos_bias),
-                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, sg, n_chunks,
-                     dw1t, dw2t, part);
-  int rc = check_launch();
+  int rc = TN_OK;
+#define TN_CPPN_BWD(KE)                                                                        \
+  hipLaunchKernelGGL(cppn_backward_kernel<KE>, dim3((unsigned)grid), dim3(kWave * kCppnWaves), \
+                     0, stream, make_view(p), t.status, t.n_valid, t.row_ptr, t.edge_src,      \
+                     reinterpret_cast<const int32_t*>(t.edge_w), t.pos_fn,                    \
+                     reinterpret_cast<const int32_t*>(t.pos_bias),                            \
+                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, sg, n_chunks,    \
+                     dw1t, dw2t, part);                                                       \
+  rc = check_launch();                                                                        \
   if (rc != TN_OK) return rc;
+  TN_CPPN_BWD(kCppnCompactEdges)
+  TN_CPPN_BWD(kCppnEdges)
+#undef TN_CPPN_BWD
   hipLaunchKernelGGL(cppn_grad_reduce_kernel, dim3((unsigned)p.P), dim3(256), 0, stream,
                      make_view(p), t.n_valid, t.row_ptr, t.edge_row, t.order, t.pos_fn, part,
                      n_chunks * kCppnWaves, dW, db);

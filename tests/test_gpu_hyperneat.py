@@ -279,6 +279,35 @@ def test_cppn_backward_full_substrate():
     _check_cppn_grads(pop, GRID, NOUT, r1, r2, u1, u2, dW, db, range(pop.P))
 
 
+def test_cppn_backward_both_slot_forms_and_edge_limit():
+    """CPPNs of 34 to 70 enabled in-edges: the compact form (at most 48
+    in-edges) and the full one (49 to 64) against the oracle, NaN above the
+    64 in-edges the adjoint holds."""
+    import paper_2504_08339_amd as tn
+    rng = np.random.default_rng(61)
+    muts = np.array([30, 46, 50, 54, 58, 62, 75, 40])
+    pop = synth.grow_population(8, 5, 1, 32, 128, muts, rng,
+                                hidden_acts=("sin", "gaussian", "tanh", "abs"),
+                                output_acts=("tanh",))
+    edges = [int((pop.conn_rows(g)["en"] > 0).sum()) for g in range(pop.P)]
+    assert min(edges) <= 48 and any(48 < e <= 64 for e in edges) and max(edges) > 64
+    grid, n_out = 8, 2
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    _, _, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
+    S = grid * grid
+    u1 = rng.standard_normal((pop.P, S, S)).astype(np.float32)
+    u2 = rng.standard_normal((pop.P, n_out, S)).astype(np.float32)
+    dW, db = tn.cppn_backward(dp, tr, torch.from_numpy(u1).cuda(), torch.from_numpy(u2).cuda(),
+                              grid, n_out, THR)
+    dW, db = host(dW), host(db)
+    over = [g for g in range(pop.P) if edges[g] > 64]
+    for g in over:
+        assert np.isnan(dW[g]).all() and np.isnan(db[g]).all()
+    _check_cppn_grads(pop, grid, n_out, host(r1), host(r2), u1, u2, dW, db,
+                      [g for g in range(pop.P) if edges[g] <= 64])
+
+
 def test_cppn_backward_through_the_substrate():
     """The whole chain: CPPN query -> substrate forward -> substrate backward ->
     CPPN adjoint, against the oracle's pipeline gradient (with the GPU's
