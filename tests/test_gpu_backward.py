@@ -77,6 +77,28 @@ def oracle_mse_grads(pop, X, T, genomes):
     return np.array(losses), np.array(dWs), np.array(dbs)
 
 
+def test_register_adjoint_limits_and_lds_fallback():
+    """Genomes of 15 to 85 enabled in-edges, on both sides of the
+    register-file adjoint's limits (at most 48 positions and 64 in-edges;
+    larger ones go to the LDS kernel), against the oracle."""
+    rng = np.random.default_rng(17)
+    muts = np.array([10, 20, 30, 40, 45, 50, 55, 60, 70, 90, 25, 35])
+    pop = synth.grow_population(len(muts), 4, 2, 64, 256, muts, rng, hidden_acts=("tanh",),
+                                output_acts=("identity",), disable_p=0.1)
+    sizes = []
+    for g in range(pop.P):
+        n = int((pop.node_rows(g)["key"] >= 0).sum())
+        e = int((pop.conn_rows(g)["en"] > 0).sum())
+        sizes.append((n, e))
+    fits = [n <= 48 and e <= 64 for n, e in sizes]
+    assert any(fits) and not all(fits) and any(48 < e <= 64 for _, e in sizes), sizes
+    X = synth.uniform_inputs(300, 4, 23)
+    T = synth.target_mlp(X, 16, 2, 24)
+    loss, dW, db = gpu_mse(pop, X, T)
+    ref_loss, ref_dW, ref_db = oracle_mse_grads(pop, X, T, range(pop.P))
+    check_grads(pop, dW, db, ref_dW, ref_db, range(pop.P))
+
+
 def test_mse_gradients_match_oracle():
     pop, X, T = _cfg3(96)
     loss, dW, db = gpu_mse(pop, X, T)
