@@ -7,9 +7,10 @@
 //         bitonic-sort them by marking, flag repeated markings, and store the
 //         sorted list position-major (keysT[k][g]) so that 64 genomes' k-th
 //         genes are 64 consecutive words.
-//   pairs block = up to 8 "row" genomes x 256 "column" genomes (see
+//   pairs block = up to kMaxRows "row" genomes x 256 "column" genomes (see
 //         pair_kernel): row genes in LDS hashes, each column gene read once
-//         and probed against every row.
+//         and probed against every row; only the pairs on or above the
+//         diagonal are evaluated, each written to both halves.
 #include <algorithm>
 
 #include "tn_internal.hpp"
@@ -168,6 +169,10 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
   const int i0 = blockIdx.y * R;
   const int j = blockIdx.x * kPairBlock + threadIdx.x;
   const int nr = min(R, P - i0);
+  // the distance is symmetric bit for bit (the matched markings are visited
+  // in ascending order from either side): only pairs j >= i are evaluated,
+  // each written to both halves of the matrix
+  if ((int)(blockIdx.x * kPairBlock + kPairBlock - 1) < i0) return;  // all below the diagonal
   for (int h = threadIdx.x; h < nr * HC; h += kPairBlock) hk_all[h] = -1;
   __syncthreads();
   for (int r = 0; r < nr; ++r) {
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
     const uint32_t h0 = (uint32_t)ws.hT[(int64_t)k * P + j] & (uint32_t)(HC - 1);
 #pragma unroll
     for (int r = 0; r < kMaxRows; ++r) {
-      if (r >= nr || ni[r] < 0) continue;
+      if (r >= nr || ni[r] < 0 || j < i0 + r) continue;
       ex[r] += key > maxi[r];
       const long long* hk = hk_all + (size_t)r * HC;
       uint32_t h = h0;
@@ -225,13 +230,17 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
   const long long maxj = ws.maxk[j];
 #pragma unroll
   for (int r = 0; r < kMaxRows; ++r) {
-    if (r >= nr) continue;
+    if (r >= nr || j < i0 + r) continue;
     const int64_t o = (int64_t)(i0 + r) * P + j;
+    const int64_t ot = (int64_t)j * P + (i0 + r);  // the mirrored entry (o itself on the diagonal)
     if (ni[r] < 0 || nj < 0) {
       dist[o] = __builtin_nanf("");
+      dist[ot] = __builtin_nanf("");
       if (E_out) {
         E_out[o] = -1;
         D_out[o] = -1;
+        E_out[ot] = -1;
+        D_out[ot] = -1;
       }
       continue;
     }
@@ -252,9 +261,12 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
       d = c1 * (float)E / fN + c2 * (float)D / fN + c3 * (M[r] > 0 ? S[r] / (float)M[r] : 0.0f);
     }
     dist[o] = d;
+    dist[ot] = d;
     if (E_out) {
       E_out[o] = E;
       D_out[o] = D;
+      E_out[ot] = E;
+      D_out[ot] = D;
     }
   }
 }
