@@ -165,7 +165,9 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs p) {
   const int per_g = p.m_tiles * p.n_tiles;
   const int g = (int)(item / per_g);
   const int r = (int)(item - (int64_t)g * per_g);
-  const int mt = r / p.n_tiles, nt = r - mt * p.n_tiles;
+  // the m tiles of one n tile are consecutive items (one workgroup): their
+  // B rows are read once, from one L2
+  const int nt = r / p.m_tiles, mt = r - nt * p.m_tiles;
   const int m0 = mt * 64, n0 = nt * 64;
   const uint16_t* A = p.a + (int64_t)g * p.a_batch;
   const uint16_t* Bm = p.b + (int64_t)g * p.b_batch;
@@ -176,19 +178,29 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
   const bf16x8 zero8 = {};
-  for (int k0 = 0; k0 < p.K; k0 += 32) {
-    bf16x8 a[4], b[4];
+  // the fragments of step k0 + 32 are loaded while step k0's MFMAs run
+  bf16x8 a[4], b[4], an[4], bn[4];
+  auto load = [&](int k0, bf16x8(&fa)[4], bf16x8(&fb)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int ra = m0 + 16 * i + li, rb = n0 + 16 * i + li;
-      a[i] = ra < p.M ? *reinterpret_cast<const bf16x8*>(A + ra * p.lda + k0 + kq) : zero8;
-      b[i] = rb < p.N ? *reinterpret_cast<const bf16x8*>(Bm + rb * p.ldb + k0 + kq) : zero8;
+      fa[i] = ra < p.M ? *reinterpret_cast<const bf16x8*>(A + ra * p.lda + k0 + kq) : zero8;
+      fb[i] = rb < p.N ? *reinterpret_cast<const bf16x8*>(Bm + rb * p.ldb + k0 + kq) : zero8;
     }
+  };
+  load(0, a, b);
+  for (int k0 = 0; k0 < p.K; k0 += 32) {
+    if (k0 + 32 < p.K) load(k0 + 32, an, bn);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = an[i];
+      b[i] = bn[i];
+    }
   }
   float* C = p.c + (int64_t)g * p.c_batch;
 #pragma unroll
