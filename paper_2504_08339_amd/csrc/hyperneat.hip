@@ -84,6 +84,7 @@ cppn_query_kernel(PopView pop, const int32_t* __restrict__ status,
   uint16_t* W2 = w2t + (int64_t)g * sg.S * sg.n_out;
   float* R1 = raw1 ? raw1 + (int64_t)g * Q1 : nullptr;
   float* R2 = raw2 ? raw2 + (int64_t)g * sg.S * sg.n_out : nullptr;
+  const int step_r = kWave / sg.grid, step_c = kWave - step_r * sg.grid;  // 64 = step_r grid + step_c
   for (int u = u0; u < u1; ++u) {
     const bool first = u * kUnit < Q1;
     const int base = first ? u * kUnit : u * kUnit - Q1;
@@ -93,17 +94,20 @@ cppn_query_kernel(PopView pop, const int32_t* __restrict__ status,
       for (int k = 0; k < K; ++k) y[k] = __builtin_nanf("");
     } else {
       // the CPPN's inputs (x_s, y_s, x_t, y_t, 1) at rows 0..4 of every tile
+      // query qq = tgt * S + src, src = rs * grid + cs, tgt = rt * grid + ct:
+      // divided once for the unit's first tile, then stepped by 64 queries
+      // per tile (S is a multiple of 64, so src wraps at most once a step)
       float xs[K], ys[K], xt[K], yt[K], one[K];
+      const int q0 = base + lane;
+      int tgt = q0 / sg.S;
+      int src = q0 - tgt * sg.S;
+      int rs = src / sg.grid, cs = src - rs * sg.grid;
+      int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int qq = base + k * kWave + lane;
-        const int tgt = qq / sg.S;
-        const int src = qq - tgt * sg.S;
-        const int rs = src / sg.grid, cs = src - rs * sg.grid;
         xs[k] = fmaf((float)cs, sg.step, -1.0f);
         ys[k] = fmaf((float)rs, sg.step, -1.0f);
         if (first) {
-          const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
           xt[k] = fmaf((float)ct, sg.step, -1.0f);
           yt[k] = fmaf((float)rt, sg.step, -1.0f);
         } else {
@@ -111,6 +115,22 @@ cppn_query_kernel(PopView pop, const int32_t* __restrict__ status,
           yt[k] = 0.0f;
         }
         one[k] = 1.0f;
+        src += kWave;
+        rs += step_r;
+        cs += step_c;
+        if (cs >= sg.grid) {
+          cs -= sg.grid;
+          ++rs;
+        }
+        if (src >= sg.S) {
+          src -= sg.S;
+          rs -= sg.grid;
+          ++tgt;
+          if (++ct == sg.grid) {
+            ct = 0;
+            ++rt;
+          }
+        }
       }
       rfk_set<R>(0, xs);
       rfk_set<R>(1, ys);
@@ -506,20 +526,23 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
   const int n_units = (Q + kCppnUnit - 1) / kCppnUnit;
   const int u0 = (chunk * W + wave) * kCppnUnitsPerWave;
   const int u1 = min(u0 + kCppnUnitsPerWave, n_units);
+  const int step_r = kWave / sg.grid, step_c = kWave - step_r * sg.grid;  // 64 = step_r grid + step_c
   for (int u = u0; u < u1; ++u) {
     const bool first = u * kCppnUnit < Q1;  // S*S is a multiple of 4096
     const int base = first ? u * kCppnUnit : u * kCppnUnit - Q1;
+    // coordinates divided once for the first tile, stepped by 64 queries for
+    // the second (as in the query kernel)
     float in[2][5], up[2];
+    int tgt = (base + lane) / sg.S;
+    int src = base + lane - tgt * sg.S;
+    int rs = src / sg.grid, cs = src - rs * sg.grid;
+    int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int qq = base + k * kWave + lane;
-      const int tgt = qq / sg.S;
-      const int src = qq - tgt * sg.S;
-      const int rs = src / sg.grid, cs = src - rs * sg.grid;
       in[k][0] = fmaf((float)cs, sg.step, -1.0f);
       in[k][1] = fmaf((float)rs, sg.step, -1.0f);
       if (first) {
-        const int rt = tgt / sg.grid, ct = tgt - rt * sg.grid;
         in[k][2] = fmaf((float)ct, sg.step, -1.0f);
         in[k][3] = fmaf((float)rt, sg.step, -1.0f);
         up[k] = dw1t[(int64_t)g * Q1 + qq];
@@ -529,6 +552,22 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
         up[k] = qq < Q2 ? dw2t[(int64_t)g * Q2 + qq] : 0.0f;
       }
       in[k][4] = 1.0f;
+      src += kWave;
+      rs += step_r;
+      cs += step_c;
+      if (cs >= sg.grid) {
+        cs -= sg.grid;
+        ++rs;
+      }
+      if (src >= sg.S) {
+        src -= sg.S;
+        rs -= sg.grid;
+        ++tgt;
+        if (++ct == sg.grid) {
+          ct = 0;
+          ++rt;
+        }
+      }
     }
     // forward, values and pre-activations by position
     for (int p = 0; p < n; ++p) {
