@@ -141,6 +141,56 @@ typedef struct tn_population {
  * data is not read). Returns TN_OK, TN_EINVAL, TN_ESHAPE or TN_EUNSUPPORTED. */
 int tn_validate_population(const tn_population* pop);
 
+/* ------------------------------------------------ the paper's float layout */
+
+/*
+ * The tensorized encoding as the paper writes it (Section 3.1): a node tensor
+ * P_N [P][N_max][5] float32 with rows n = [k, bias, response, act, agg] and a
+ * connection tensor P_C [P][C_max][4] float32 with rows c = [k_in, k_out, e, w]
+ * (markings, then the enabled flag, then the attribute), both padded with
+ * NaN rows. tn_pack_paper_layout converts them into the structure-of-arrays
+ * form every other call reads (padded layout, [P][N_max] / [P][C_max]):
+ *   - a row whose first column is NaN is a padding row, wherever it sits, and
+ *     becomes an empty row (key -1 / markings -1, other fields 0);
+ *   - keys and markings must be integers 0 <= k < 2^24 (exact in float32),
+ *     act and agg integer codes 0..255 (codes outside tn_act / tn_agg are
+ *     left for tn_transform's TN_BAD_ATTR), e exactly 0 or 1; bias, response
+ *     and weight are copied bitwise.
+ * A row that breaks these rules sets its genome's bits in pack_err and is
+ * written as an empty row; the call then returns TN_EINVAL (the other rows
+ * are still converted).
+ *
+ *   PN, PC    device float32 arrays as above (caller-owned, read only; PC must
+ *             be 16-byte aligned)
+ *   out       device destination arrays (caller-owned): node_* [P][N_max],
+ *             conn_* [P][C_max]
+ *   pack_err  device int32 [P] (caller-owned): tn_pack_error bits per genome
+ * This call SYNCHRONISES `stream`: it reads pack_err back to decide its
+ * return value. TN_EINVAL also for null pointers or negative sizes.
+ */
+typedef struct tn_population_arrays {
+    int32_t* node_key;
+    float*   node_bias;
+    float*   node_resp;
+    uint8_t* node_act;
+    uint8_t* node_agg;
+    int32_t* conn_in;
+    int32_t* conn_out;
+    float*   conn_w;
+    uint8_t* conn_en;
+} tn_population_arrays;
+
+enum tn_pack_error {
+    TN_PACK_NODE_KEY = 1,    /* node key not an integer in [0, 2^24)             */
+    TN_PACK_NODE_CODE = 2,   /* act or agg not an integer code in [0, 255]        */
+    TN_PACK_CONN_KEY = 4,    /* k_in or k_out not an integer in [0, 2^24)         */
+    TN_PACK_CONN_FLAG = 8    /* enabled flag neither 0 nor 1                      */
+};
+
+int tn_pack_paper_layout(const float* PN, const float* PC, int32_t P, int32_t N_max,
+                         int32_t C_max, const tn_population_arrays* out, int32_t* pack_err,
+                         hipStream_t stream);
+
 /* --------------------------------------------------- the transformation */
 
 /*
@@ -201,7 +251,8 @@ int tn_validate_population(const tn_population* pop);
  *                        response bits; word 3 = index (in the conn block of
  *                        prog_edge) of the node's 7th in-edge; words 4..15 its
  *                        first 6 in-edges as {source prog row, weight bits},
- *                        unused slots {prog_rows, +0}
+ *                        unused slots {prog_rows, +0} (never read: a reader
+ *                        takes only the in-edge count of slots)
  */
 typedef struct tn_transformed {
     int32_t* status;
@@ -486,6 +537,11 @@ int tn_cppn_backward(const tn_population* pop, const tn_transformed* tr, const t
  * The forward pass is recomputed inside the call (nothing is saved by
  * tn_forward). Batch sums run in a fixed order, so results are deterministic.
  * A flagged genome gets NaN in all its rows.
+ * Limits: genomes with at most 48 positions, 64 enabled connections and sum or
+ * mean aggregations take a register-file adjoint; the others take an LDS
+ * adjoint holding N_max rows of 65 values and of 65 gradients. When that
+ * exceeds the device's LDS (N_max above about 300 on MI355X) those other
+ * genomes get NaN gradients (the call still returns TN_OK).
  */
 int tn_backward(const tn_population* pop, const tn_transformed* tr,
                 const float* obs, int64_t obs_genome_stride, int32_t B,

@@ -23,6 +23,8 @@ TN_MAX_NODES, TN_MAX_CONNS, TN_MAX_IO = 1024, 4096, 1024
 TN_CYCLE, TN_DANGLING, TN_DUP_CONN, TN_DUP_NODE = 1, 2, 4, 8
 TN_INPUT_DST, TN_MISSING_IO, TN_OVERSIZE, TN_BAD_ATTR = 16, 32, 64, 128
 TN_ENGINE_AUTO, TN_ENGINE_LDS, TN_ENGINE_REG = 0, 1, 2
+# tn_pack_paper_layout error bits
+TN_PACK_NODE_KEY, TN_PACK_NODE_CODE, TN_PACK_CONN_KEY, TN_PACK_CONN_FLAG = 1, 2, 4, 8
 
 
 class TnPopulation(ctypes.Structure):
@@ -53,6 +55,12 @@ class TnTransformedElems(ctypes.Structure):
                 ("io_elems", ctypes.c_int64)]
 
 
+class TnPopulationArrays(ctypes.Structure):
+    _fields_ = [("node_key", c_int32_p), ("node_bias", c_float_p), ("node_resp", c_float_p),
+                ("node_act", c_uint8_p), ("node_agg", c_uint8_p), ("conn_in", c_int32_p),
+                ("conn_out", c_int32_p), ("conn_w", c_float_p), ("conn_en", c_uint8_p)]
+
+
 class TnTile(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("obs_per_lane", ctypes.c_int32),
                 ("waves_per_genome", ctypes.c_int32), ("rows", ctypes.c_int32)]
@@ -79,6 +87,9 @@ SIGNATURES = {
     "tn_validate_population": (ctypes.c_int, [_POP]),
     "tn_transformed_size": (ctypes.c_int, [_POP, ctypes.POINTER(TnTransformedElems)]),
     "tn_transform": (ctypes.c_int, [_POP, _TR, _STREAM]),
+    "tn_pack_paper_layout": (ctypes.c_int, [c_float_p, c_float_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.POINTER(TnPopulationArrays),
+                                            c_int32_p, _STREAM]),
     "tn_forward": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,
                                   c_float_p, _STREAM]),
     "tn_forward_tiled": (ctypes.c_int, [_POP, _TR, c_float_p, ctypes.c_int64, ctypes.c_int32,

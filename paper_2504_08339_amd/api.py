@@ -35,6 +35,23 @@ def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _need(t, name, dtype, shape, device):
+    """Raises before any launch unless ``t`` is a contiguous ``dtype`` tensor of
+    exactly ``shape`` on ``device`` (a host tensor or a short buffer would hand
+    a kernel an address it must not read)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
 def _check(name, rc):
     if rc != _abi.TN_OK:
         text = _lib.tn_status_string(rc).decode()
@@ -55,22 +72,31 @@ class Population:
                  conn_off: Optional[torch.Tensor] = None):
         self.n_in, self.n_out, self.N_max, self.C_max = int(n_in), int(n_out), int(N_max), int(C_max)
         self.t = {}
-        for name, dt in {**_NODE, **_CONN}.items():
-            x = tensors[name]
-            if x.dtype != dt or not x.is_contiguous():
-                raise TypeError(f"{name} must be a contiguous {dt} tensor")
-            self.t[name] = x
-        self.device = self.t["node_key"].device
+        key = tensors["node_key"]
+        if not isinstance(key, torch.Tensor) or key.device.type != "cuda":
+            raise ValueError("population tensors must be on a GPU device")
+        self.device = key.device
         self.node_off, self.conn_off = node_off, conn_off
         if node_off is not None:
-            for o in (node_off, conn_off):
-                if o is None or o.dtype != torch.int64 or not o.is_contiguous():
-                    raise TypeError("node_off / conn_off must be contiguous int64 tensors")
-            self.P = node_off.numel() - 1
-            total_nodes, total_conns = self.t["node_key"].numel(), self.t["conn_in"].numel()
+            if conn_off is None:
+                raise TypeError("node_off and conn_off go together")
+            P = node_off.numel() - 1
+            for name, o in (("node_off", node_off), ("conn_off", conn_off)):
+                _need(o, name, torch.int64, (P + 1,), self.device)
+            if P < 0:
+                raise ValueError("node_off must hold P+1 >= 1 offsets")
+            # the array lengths must be what the offsets say (one read back)
+            total_nodes, total_conns = int(node_off[-1]), int(conn_off[-1])
+            node_shape, conn_shape = (total_nodes,), (total_conns,)
+            self.P = P
         else:
-            self.P = self.t["node_key"].shape[0] if self.t["node_key"].dim() == 2 else 0
+            self.P = key.shape[0] if key.dim() == 2 else 0
+            node_shape, conn_shape = (self.P, self.N_max), (self.P, self.C_max)
             total_nodes, total_conns = self.P * self.N_max, self.P * self.C_max
+        for name, dt in _NODE.items():
+            self.t[name] = _need(tensors[name], name, dt, node_shape, self.device)
+        for name, dt in _CONN.items():
+            self.t[name] = _need(tensors[name], name, dt, conn_shape, self.device)
         self.c = TnPopulation(
             self.P, self.n_in, self.n_out, self.N_max, self.C_max, total_nodes, total_conns,
             _p(node_off, _abi.c_int64_p), _p(conn_off, _abi.c_int64_p),
@@ -96,6 +122,38 @@ class Population:
             node_off = dev(node_off, torch.int64)
             conn_off = dev(conn_off, torch.int64)
         return cls(n_in, n_out, N_max, C_max, ts, node_off, conn_off)
+
+
+def pack_paper_layout(PN: torch.Tensor, PC: torch.Tensor, n_in: int, n_out: int,
+                      return_errors: bool = False):
+    """Population from the paper's float tensors (Section 3.1): PN [P][N_max][5]
+    rows [k, bias, response, act, agg], PC [P][C_max][4] rows [k_in, k_out, e, w],
+    NaN padding rows anywhere. Raises TNError (TN_EINVAL) when a row breaks the
+    encoding's rules, unless ``return_errors``: then returns (population,
+    per-genome tn_pack_error bits [P], status code). Synchronises the stream."""
+    if not isinstance(PN, torch.Tensor) or PN.dim() != 3 or PN.device.type != "cuda":
+        raise ValueError("PN must be a [P][N_max][5] GPU tensor")
+    P, N_max, d = PN.shape[0], PN.shape[1], PN.device
+    _need(PN, "PN", torch.float32, (P, N_max, 5), d)
+    if not isinstance(PC, torch.Tensor) or PC.dim() != 3:
+        raise ValueError("PC must be a [P][C_max][4] tensor")
+    C_max = PC.shape[1]
+    _need(PC, "PC", torch.float32, (P, C_max, 4), d)
+    ts = {k: torch.empty((P, N_max), dtype=dt, device=d) for k, dt in _NODE.items()}
+    ts.update({k: torch.empty((P, C_max), dtype=dt, device=d) for k, dt in _CONN.items()})
+    arrays = _abi.TnPopulationArrays(*[_p(ts[k], ty) for k, ty in (
+        ("node_key", _abi.c_int32_p), ("node_bias", _abi.c_float_p),
+        ("node_resp", _abi.c_float_p), ("node_act", _abi.c_uint8_p),
+        ("node_agg", _abi.c_uint8_p), ("conn_in", _abi.c_int32_p), ("conn_out", _abi.c_int32_p),
+        ("conn_w", _abi.c_float_p), ("conn_en", _abi.c_uint8_p))])
+    err = torch.empty(max(P, 1), dtype=torch.int32, device=d)
+    rc = _lib.tn_pack_paper_layout(_p(PN, _abi.c_float_p), _p(PC, _abi.c_float_p), P, N_max,
+                                   C_max, ctypes.byref(arrays), _p(err, _abi.c_int32_p),
+                                   _stream(d))
+    if not (return_errors and rc == _abi.TN_EINVAL):
+        _check("tn_pack_paper_layout", rc)
+    pop = Population(n_in, n_out, N_max, C_max, ts)
+    return (pop, err[:P], rc) if return_errors else pop
 
 
 class Transformed:
@@ -143,13 +201,33 @@ def transform(pop: Population, out: Optional[Transformed] = None) -> Transformed
 
 
 def _obs_stride(pop: Population, obs: torch.Tensor):
-    if obs.dtype != torch.float32 or not obs.is_contiguous():
-        raise TypeError("obs must be a contiguous float32 tensor")
+    """(B, per-genome stride) of observations [B][n_in] (shared) or [P][B][n_in]."""
+    if not isinstance(obs, torch.Tensor) or obs.dim() not in (2, 3):
+        raise ValueError("obs must be [B][n_in] (shared) or [P][B][n_in]")
+    B = obs.shape[-2]
     if obs.dim() == 2:
-        return obs.shape[0], 0
-    if obs.dim() == 3 and obs.shape[0] == pop.P:
-        return obs.shape[1], obs.shape[1] * obs.shape[2]
-    raise ValueError("obs must be [B][n_in] (shared) or [P][B][n_in]")
+        _need(obs, "obs", torch.float32, (B, pop.n_in), pop.device)
+        return B, 0
+    _need(obs, "obs", torch.float32, (pop.P, B, pop.n_in), pop.device)
+    return B, B * pop.n_in
+
+
+def _per_genome(pop: Population, t: torch.Tensor, name: str, B: int):
+    """Stride of a [B][n_out] (shared) or [P][B][n_out] float32 tensor."""
+    if not isinstance(t, torch.Tensor) or t.dim() not in (2, 3):
+        raise ValueError(f"{name} must be [B][n_out] (shared) or [P][B][n_out]")
+    if t.dim() == 2:
+        _need(t, name, torch.float32, (B, pop.n_out), pop.device)
+        return 0
+    _need(t, name, torch.float32, (pop.P, B, pop.n_out), pop.device)
+    return B * pop.n_out
+
+
+def _out(pop: Population, out, B: int):
+    shape = (pop.P, B, pop.n_out)
+    if out is None:
+        return torch.empty(shape, dtype=torch.float32, device=pop.device)
+    return _need(out, "out", torch.float32, shape, pop.device)
 
 
 def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
@@ -160,8 +238,7 @@ def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
     and ``rows`` only change how the work is laid out on the chip (0 = library
     choice); a genome needing more value rows than ``rows`` gets NaN outputs."""
     B, stride = _obs_stride(pop, obs)
-    if out is None:
-        out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
+    out = _out(pop, out, B)
     tile = _abi.TnTile(engine, obs_per_lane, waves_per_genome, rows)
     _check("tn_forward_tiled", _lib.tn_forward_tiled(
         ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
@@ -173,10 +250,7 @@ def forward_loss(pop: Population, tr: Transformed, obs: torch.Tensor, target: to
                  scale: float = 1.0, offset: float = 0.0, store_outputs: bool = True):
     """(loss [P], outputs or None): loss[g] = offset + scale * sum (y - target)^2."""
     B, stride = _obs_stride(pop, obs)
-    if target.dim() == 2:
-        tstride = 0
-    else:
-        tstride = target.shape[1] * target.shape[2]
+    tstride = _per_genome(pop, target, "target", B)
     out = (torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device=pop.device)
            if store_outputs else None)
     loss = torch.empty(max(pop.P, 1), dtype=torch.float32, device=pop.device)
@@ -196,8 +270,7 @@ def _grad_buffers(pop: Population):
 def backward(pop: Population, tr: Transformed, obs: torch.Tensor, dY: torch.Tensor):
     """(dW, db) shaped like conn_w / node_bias, for upstream gradient dY [P][B][n_out]."""
     B, stride = _obs_stride(pop, obs)
-    if dY.dtype != torch.float32 or not dY.is_contiguous() or dY.shape != (pop.P, B, pop.n_out):
-        raise ValueError("dY must be a contiguous float32 [P][B][n_out] tensor")
+    _need(dY, "dY", torch.float32, (pop.P, B, pop.n_out), pop.device)
     dW, db = _grad_buffers(pop)
     _check("tn_backward", _lib.tn_backward(
         ctypes.byref(pop.c), ctypes.byref(tr.c), _p(obs, _abi.c_float_p), stride, B,
@@ -211,7 +284,7 @@ def forward_backward_mse(pop: Population, tr: Transformed, obs: torch.Tensor,
     """(loss [P], dW, db): mean squared error against target ([B][n_out] shared or
     [P][B][n_out]) and its gradient with respect to weights and biases."""
     B, stride = _obs_stride(pop, obs)
-    tstride = 0 if target.dim() == 2 else target.shape[1] * target.shape[2]
+    tstride = _per_genome(pop, target, "target", B)
     dW, db = _grad_buffers(pop)
     loss = torch.empty(max(pop.P, 1), dtype=torch.float32, device=pop.device)
     _check("tn_forward_backward_mse", _lib.tn_forward_backward_mse(
@@ -226,7 +299,8 @@ class DistanceWorkspace:
         n = ctypes.c_size_t()
         _check("tn_distance_workspace_size",
                _lib.tn_distance_workspace_size(ctypes.byref(pop.c), ctypes.byref(n)))
-        self.buf = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=pop.device)
+        self.nbytes = int(n.value)
+        self.buf = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=pop.device)
 
 
 def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
@@ -240,6 +314,14 @@ def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
         D = torch.empty((P, P), dtype=torch.int32, device=pop.device) if counts else None
     else:
         dist, E, D = out
+        _need(dist, "dist", torch.float32, (P, P), pop.device)
+        if (E is None) != (D is None):
+            raise ValueError("excess and disjoint go together")
+        if E is not None:
+            _need(E, "excess", torch.int32, (P, P), pop.device)
+            _need(D, "disjoint", torch.int32, (P, P), pop.device)
+    if ws.buf.device != pop.device or ws.buf.numel() < ws.nbytes:
+        raise ValueError("distance workspace from another population or device")
     _check("tn_distance", _lib.tn_distance(
         ctypes.byref(pop.c), c1, c2, c3, ctypes.c_void_p(ws.buf.data_ptr()),
         _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p), _p(D, _abi.c_int32_p),
@@ -286,9 +368,7 @@ class Plan:
         B, stride = _obs_stride(self.pop, obs)
         if B != self.B:
             raise ValueError(f"the plan was made for B={self.B}, got {B}")
-        if out is None:
-            out = torch.empty((self.pop.P, B, self.pop.n_out), dtype=torch.float32,
-                              device=self.pop.device)
+        out = _out(self.pop, out, B)
         _check(name, getattr(_lib, name)(self._h, _p(obs, _abi.c_float_p), stride,
                                          _p(out, _abi.c_float_p), _stream(self.pop.device)))
         return out
@@ -302,6 +382,9 @@ class Plan:
     def forward_bucket(self, i: int, obs: torch.Tensor, out: torch.Tensor,
                        persistent: bool = True) -> torch.Tensor:
         B, stride = _obs_stride(self.pop, obs)
+        if B != self.B:
+            raise ValueError(f"the plan was made for B={self.B}, got {B}")
+        out = _out(self.pop, out, B)
         _check("tn_plan_forward_bucket", _lib.tn_plan_forward_bucket(
             self._h, i, 1 if persistent else 0, _p(obs, _abi.c_float_p), stride,
             _p(out, _abi.c_float_p), _stream(self.pop.device)))
@@ -310,9 +393,9 @@ class Plan:
     def tune(self, obs: torch.Tensor, out: Optional[torch.Tensor] = None,
              tune_cache: Optional[str] = None) -> None:
         B, stride = _obs_stride(self.pop, obs)
-        if out is None:
-            out = torch.empty((self.pop.P, B, self.pop.n_out), dtype=torch.float32,
-                              device=self.pop.device)
+        if B != self.B:
+            raise ValueError(f"the plan was made for B={self.B}, got {B}")
+        out = _out(self.pop, out, B)
         _check("tn_plan_tune", _lib.tn_plan_tune(
             self._h, _p(obs, _abi.c_float_p), stride, _p(out, _abi.c_float_p),
             tune_cache.encode() if tune_cache else None, _stream(self.pop.device)))
@@ -341,30 +424,38 @@ def cppn_query(pop: Population, tr: Transformed, grid: int = 32, n_out: int = 8,
     return (w1t, w2t, r1, r2) if raw else (w1t, w2t)
 
 
+def _x_layout(x: torch.Tensor, P: int, S: int):
+    """(B, stride) of substrate inputs x: [B][S] shared or [P][B][S] bfloat16."""
+    if not isinstance(x, torch.Tensor) or x.dim() not in (2, 3):
+        raise ValueError("x must be [B][S] (shared) or [P][B][S]")
+    B = x.shape[-2]
+    if x.dim() == 2:
+        _need(x, "x", torch.bfloat16, (B, S), x.device)
+        return B, 0
+    _need(x, "x", torch.bfloat16, (P, B, S), x.device)
+    return B, B * S
+
+
 def substrate_forward(w1t: torch.Tensor, w2t: torch.Tensor, x: torch.Tensor, grid: int = 32,
                       n_out: int = 8, threshold: float = 0.2):
     """(h [P][B][S] float32, y [P][B][n_out] float32) for bfloat16 inputs x
     ([B][S] shared or [P][B][S])."""
-    if x.dtype != torch.bfloat16 or not x.is_contiguous():
-        raise TypeError("x must be a contiguous bfloat16 tensor")
-    for w in (w1t, w2t):
-        if w.dtype != torch.bfloat16 or not w.is_contiguous():
-            raise TypeError("weights must be contiguous bfloat16 tensors")
     sub = _substrate(grid, n_out, threshold)
     S = int(grid) * int(grid)
-    P = w1t.shape[0]
-    if x.dim() == 2:
-        B, stride = x.shape[0], 0
-    else:
-        B, stride = x.shape[1], x.shape[1] * x.shape[2]
-    if x.shape[-1] != S:
-        raise ValueError("x must have grid*grid columns")
-    h = torch.empty((P, B, S), dtype=torch.float32, device=x.device)
-    y = torch.empty((P, B, n_out), dtype=torch.float32, device=x.device)
+    if not isinstance(w1t, torch.Tensor) or w1t.dim() != 3 or w1t.device.type != "cuda":
+        raise ValueError("w1t must be a [P][S][S] GPU tensor")
+    P, d = w1t.shape[0], w1t.device
+    _need(w1t, "w1t", torch.bfloat16, (P, S, S), d)
+    _need(w2t, "w2t", torch.bfloat16, (P, n_out, S), d)
+    B, stride = _x_layout(x, P, S)
+    if x.device != d:
+        raise ValueError("x must be on the weights' device")
+    h = torch.empty((P, B, S), dtype=torch.float32, device=d)
+    y = torch.empty((P, B, n_out), dtype=torch.float32, device=d)
     _check("tn_substrate_forward", _lib.tn_substrate_forward(
         ctypes.byref(sub), P, ctypes.c_void_p(w1t.data_ptr()), ctypes.c_void_p(w2t.data_ptr()),
         ctypes.c_void_p(x.data_ptr()), stride, B, _p(h, _abi.c_float_p), _p(y, _abi.c_float_p),
-        _stream(x.device)))
+        _stream(d)))
     return h, y
 
 
@@ -374,22 +465,25 @@ def substrate_backward(w2t: torch.Tensor, x: torch.Tensor, h: torch.Tensor, dy: 
     with respect to the substrate weights the forward used."""
     sub = _substrate(grid, n_out, threshold)
     S = int(grid) * int(grid)
-    P = w2t.shape[0]
-    B, stride = (x.shape[0], 0) if x.dim() == 2 else (x.shape[1], x.shape[1] * x.shape[2])
-    for t, dt in ((w2t, torch.bfloat16), (x, torch.bfloat16), (h, torch.float32),
-                  (dy, torch.float32)):
-        if t.dtype != dt or not t.is_contiguous():
-            raise TypeError("w2t, x: contiguous bfloat16; h, dy: contiguous float32")
+    if not isinstance(w2t, torch.Tensor) or w2t.dim() != 3 or w2t.device.type != "cuda":
+        raise ValueError("w2t must be a [P][n_out][S] GPU tensor")
+    P, d = w2t.shape[0], w2t.device
+    _need(w2t, "w2t", torch.bfloat16, (P, n_out, S), d)
+    B, stride = _x_layout(x, P, S)
+    if x.device != d:
+        raise ValueError("x must be on the weights' device")
+    _need(h, "h", torch.float32, (P, B, S), d)
+    _need(dy, "dy", torch.float32, (P, B, n_out), d)
     n = ctypes.c_size_t()
     _check("tn_substrate_workspace_size", _lib.tn_substrate_workspace_size(
         ctypes.byref(sub), P, B, stride, ctypes.byref(n)))
-    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=x.device)
-    dw1t = torch.empty((P, S, S), dtype=torch.float32, device=x.device)
-    dw2t = torch.empty((P, n_out, S), dtype=torch.float32, device=x.device)
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=d)
+    dw1t = torch.empty((P, S, S), dtype=torch.float32, device=d)
+    dw2t = torch.empty((P, n_out, S), dtype=torch.float32, device=d)
     _check("tn_substrate_backward", _lib.tn_substrate_backward(
         ctypes.byref(sub), P, ctypes.c_void_p(w2t.data_ptr()), ctypes.c_void_p(x.data_ptr()),
         stride, B, _p(h, _abi.c_float_p), _p(dy, _abi.c_float_p), ctypes.c_void_p(ws.data_ptr()),
-        _p(dw1t, _abi.c_float_p), _p(dw2t, _abi.c_float_p), _stream(x.device)))
+        _p(dw1t, _abi.c_float_p), _p(dw2t, _abi.c_float_p), _stream(d)))
     return dw1t, dw2t
 
 
@@ -400,9 +494,9 @@ def cppn_backward(pop: Population, tr: Transformed, dw1t: torch.Tensor, dw2t: to
     threshold (dw1t [P][S][S], dw2t [P][n_out][S] float32, as from
     substrate_backward)."""
     sub = _substrate(grid, n_out, threshold)
-    for t in (dw1t, dw2t):
-        if t.dtype != torch.float32 or not t.is_contiguous():
-            raise TypeError("dw1t and dw2t must be contiguous float32 tensors")
+    S = int(grid) * int(grid)
+    _need(dw1t, "dw1t", torch.float32, (pop.P, S, S), pop.device)
+    _need(dw2t, "dw2t", torch.float32, (pop.P, n_out, S), pop.device)
     n = ctypes.c_size_t()
     _check("tn_cppn_backward_workspace_size", _lib.tn_cppn_backward_workspace_size(
         ctypes.byref(pop.c), ctypes.byref(sub), ctypes.byref(n)))

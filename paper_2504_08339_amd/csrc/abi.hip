@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "fwd_launch.hpp"
 #include "tn_internal.hpp"
@@ -32,6 +33,8 @@ size_t cppn_backward_workspace_bytes(const tn_population& p, const tn_substrate&
 int launch_cppn_backward(const tn_population& p, const tn_transformed& t, const tn_substrate& sub,
                          const float* dw1t, const float* dw2t, void* workspace, float* dW,
                          float* db, hipStream_t stream);
+int launch_pack(const float* PN, const float* PC, int P, int N_max, int C_max,
+                const tn_population_arrays& out, int32_t* err, hipStream_t stream);
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
@@ -141,6 +144,29 @@ int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out) {
   out->conn_elems = conn_elems(pop);
   out->genome_elems = pop->P;
   out->io_elems = (int64_t)pop->P * (pop->n_in + pop->n_out);
+  return TN_OK;
+}
+
+int tn_pack_paper_layout(const float* PN, const float* PC, int32_t P, int32_t N_max,
+                         int32_t C_max, const tn_population_arrays* out, int32_t* pack_err,
+                         hipStream_t stream) {
+  if (P < 0 || N_max < 1 || C_max < 1 || !out) return TN_EINVAL;
+  if (N_max > TN_MAX_NODES || C_max > TN_MAX_CONNS) return TN_EUNSUPPORTED;
+  if (P == 0) return TN_OK;
+  if (!PN || !PC || !pack_err || !out->node_key || !out->node_bias || !out->node_resp ||
+      !out->node_act || !out->node_agg || !out->conn_in || !out->conn_out || !out->conn_w ||
+      !out->conn_en)
+    return TN_EINVAL;
+  if (reinterpret_cast<uintptr_t>(PC) % 16 != 0) return TN_EINVAL;
+  int rc = launch_pack(PN, PC, P, N_max, C_max, *out, pack_err, stream);
+  if (rc != TN_OK) return rc;
+  std::vector<int32_t> err((size_t)P);
+  rc = record_hip(hipMemcpyAsync(err.data(), pack_err, sizeof(int32_t) * (size_t)P,
+                                 hipMemcpyDeviceToHost, stream));
+  if (rc == TN_OK) rc = record_hip(hipStreamSynchronize(stream));
+  if (rc != TN_OK) return rc;
+  for (int32_t e : err)
+    if (e) return TN_EINVAL;
   return TN_OK;
 }
 

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
     const int32_t* __restrict__ src, const int32_t* __restrict__ w_bits,
     const int32_t* __restrict__ edge_row, const int32_t* __restrict__ fn,
     const int32_t* __restrict__ bias_bits, const int32_t* __restrict__ resp_bits,
-    const int32_t* __restrict__ io_pos, const float* __restrict__ obs, BwdArgs a) {
+    const int32_t* __restrict__ io_pos, const float* __restrict__ obs, BwdArgs a, int lds_ok) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int g = blockIdx.x;
   const int lane = lane_id();
@@ -172,7 +172,9 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
     const int n0 = n_valid[g];
     if (rf_bwd_eligible(st, n0, st ? 0 : row_ptr[rb + n0], fn + nb)) return;  // backward_rf_kernel's
   }
-  if (st) {
+  // flagged genomes, and (when N_max rows of values and gradients exceed the
+  // device's LDS) every genome the register-file adjoint could not take
+  if (st || !lds_ok) {
     const float nan = __builtin_nanf("");
     for (int64_t r = lane; r < crows; r += kWave) a.dW[cb + r] = nan;
     for (int64_t r = lane; r < nrows; r += kWave) a.db[nb + r] = nan;
@@ -567,8 +569,16 @@ int launch_backward(const tn_population& p, const tn_transformed& t, const float
                     int64_t obs_stride, int B, const float* dY, int64_t dY_stride,
                     const float* target, int64_t target_stride, float scale, float* loss,
                     float* dW, float* db, hipStream_t stream) {
-  const size_t lds = bwd_lds(p.N_max, p.C_max, p.n_in + p.n_out).bytes;
+  // The LDS adjoint holds N_max rows of values and of gradients; above the
+  // device's LDS (N_max beyond about 300) it only writes NaN for the genomes
+  // the register-file adjoint leaves to it, and the call still succeeds.
+  size_t lds = bwd_lds(p.N_max, p.C_max, p.n_in + p.n_out).bytes;
   int rc = allow_lds((const void*)backward_kernel, lds);
+  const int lds_ok = rc == TN_OK;
+  if (rc == TN_EUNSUPPORTED) {
+    lds = 0;
+    rc = TN_OK;
+  }
   if (rc != TN_OK || p.P == 0) return rc;
   BwdArgs a{obs_stride, B, dY, dY_stride, target, target_stride, scale, loss, dW, db};
   hipLaunchKernelGGL(backward_rf_kernel, dim3(p.P), dim3(kWave), 0, stream, make_view(p),
@@ -582,7 +592,7 @@ int launch_backward(const tn_population& p, const tn_transformed& t, const float
                      t.n_valid, t.order, t.row_ptr, t.edge_src,
                      reinterpret_cast<const int32_t*>(t.edge_w), t.edge_row, t.pos_fn,
                      reinterpret_cast<const int32_t*>(t.pos_bias),
-                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, obs, a);
+                     reinterpret_cast<const int32_t*>(t.pos_resp), t.io_pos, obs, a, lds_ok);
   return check_launch();
 }
 

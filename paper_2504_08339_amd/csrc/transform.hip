@@ -556,8 +556,9 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   // order; inputs are staged separately): word 0 = act | agg << 3 | row << 6 |
   // in-edge count << 17, word 1 bias, word 2 response, word 3 the in-edge
   // list index of the node's 7th in-edge (for nodes with more than 6), words
-  // 4..15 its first 6 in-edges as (source row, weight); unused slots read the
-  // zero row (row prog_rows, which the kernel clears) with weight +0.
+  // 4..15 its first 6 in-edges as (source row, weight); unused slots hold
+  // (prog_rows, +0), a row past every live value: the engines read only the
+  // record's in-edge count of slots, so these entries are never dereferenced.
   {
     const int zrow = pop.n_in + n_new;
     int in_before = 0;

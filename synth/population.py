@@ -508,3 +508,21 @@ def subset(pop: Population, genomes: Sequence[int]) -> Population:
                       cat(nb, "key"), cat(nb, "bias"), cat(nb, "resp"), cat(nb, "act"),
                       cat(nb, "agg"), cat(cb, "in"), cat(cb, "out"), cat(cb, "w"),
                       cat(cb, "en"), node_off, conn_off)
+
+
+def to_paper_layout(pop: Population):
+    """The population as the paper's float tensors (Section 3.1): P_N [P][N_max][5]
+    rows [k, bias, response, act, agg] and P_C [P][C_max][4] rows [k_in, k_out, e, w],
+    with every empty row all NaN (padded populations only)."""
+    assert not pop.ragged
+    P = pop.P
+    PN = np.full((P, pop.N_max, 5), np.nan, np.float32)
+    PC = np.full((P, pop.C_max, 4), np.nan, np.float32)
+    nv = pop.node_key >= 0
+    cv = (pop.conn_in >= 0) & (pop.conn_out >= 0)
+    for j, a in enumerate((pop.node_key, pop.node_bias, pop.node_resp, pop.node_act,
+                           pop.node_agg)):
+        PN[..., j] = np.where(nv, a.astype(np.float32), np.float32(np.nan))
+    for j, a in enumerate((pop.conn_in, pop.conn_out, pop.conn_en, pop.conn_w)):
+        PC[..., j] = np.where(cv, a.astype(np.float32), np.float32(np.nan))
+    return PN, PC

@@ -29,7 +29,22 @@ def gpu_forward(pop, obs):
     return host(tn.forward(dp, tr, tensor(obs)))
 
 
+def compare_all(Y, ref, cond, status):
+    """Whole-population comparison against oracle_pool references; returns the
+    worst |err| / cond over every output of every valid genome."""
+    bad_flag = status != 0
+    assert np.isnan(Y[bad_flag]).all()
+    Yv = Y[~bad_flag].astype(np.float64)
+    rv, cv = ref[~bad_flag], cond[~bad_flag]
+    err = np.abs(Yv - rv)
+    bad = err > RTOL * cv + ABS_FLOOR
+    assert not bad.any(), (int(bad.sum()), float(err[bad].max()))
+    pos = cv > 0
+    return float((err[pos] / cv[pos]).max()) if pos.any() else 0.0
+
+
 def check(pop, obs, Y, genomes=None):
+    """Asserts the bar on every listed genome and returns the worst |err| / cond."""
     idx = range(pop.P) if genomes is None else genomes
     worst = 0.0
     for g in idx:
@@ -82,20 +97,22 @@ def test_control_tiles_and_ragged_tail():
     obs = synth.normal_obs(64, 200, 17, 102)   # 3 full tiles + a tail of 8
     Y = gpu_forward(pop, obs)
     worst = check(pop, obs, Y)
-    print("worst err/cond", worst)
+    print(f"control tiles: worst |err|/cond {worst:.3e}")
 
 
-def test_control_full_size_sampled():
+def test_control_full_size_all_genomes():
     """The full control-policy workload (1000 genomes x 1000 observations) in the
-    launch configuration the benchmark times; outputs of 24 sampled genomes
-    (all their observations) against the oracle."""
+    launch configuration the benchmark times; every output of every genome
+    against the oracle (computed in parallel worker processes)."""
+    import oracle_pool
     pop = synth.control_population()
     obs = synth.normal_obs(pop.P, 1000, 17, 102)
     Y = gpu_forward(pop, obs)
     assert Y.shape == (1000, 1000, 6)
     assert np.isfinite(Y).all()
-    sample = np.random.default_rng(0).choice(pop.P, 24, replace=False)
-    check(pop, obs, Y, sample.tolist())
+    ref, cond, st = oracle_pool.forward_reference("control", pop.P)
+    worst = compare_all(Y, ref, cond, st)
+    print(f"control 1000 x 1000: worst |err|/cond {worst:.3e}")
 
 
 @pytest.mark.parametrize("B", [130, 300])

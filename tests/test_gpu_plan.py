@@ -125,22 +125,39 @@ def test_flagged_and_empty():
     assert pe.forward(tensor(np.zeros((5, 27), np.float32))).shape == (0, 5, 8)
 
 
-def test_full_batching_workload_sampled():
-    """10000 uneven genomes x 256 observations, the benchmark's configuration:
-    persistent graph form equals the per-bucket form bitwise; 12 sampled
-    genomes against the oracle."""
+def test_full_batching_workload_all_genomes():
+    """10000 uneven genomes x 256 observations, the benchmark's configuration
+    (a tuned plan): persistent graph form equals the per-bucket form bitwise;
+    every output of every genome against the oracle, with the worst
+    |err| / cond reported per plan bucket."""
+    import oracle_pool
     import paper_2504_08339_amd as tn
+    from gpu_util import bucket_members
+    from test_gpu_forward import ABS_FLOOR, RTOL
     pop = synth.batching_population()
     obs = synth.normal_obs(pop.P, 256, pop.n_in, 103)
     dp = to_device(pop)
     tr = tn.transform(dp)
     xt = tensor(obs)
     plan = tn.Plan(dp, tr, 256)
+    plan.tune(xt)
     a = plan.forward(xt)
     b = plan.forward_buckets(xt)
     assert np.array_equal(_bits(a), _bits(b))
-    sample = np.random.default_rng(2).choice(pop.P, 12, replace=False).tolist()
-    check(pop, obs, host(a), sample)
+    Y = host(a).astype(np.float64)
+    ref, cond, st = oracle_pool.forward_reference("batching", pop.P)
+    assert np.isnan(Y[st != 0]).all()
+    members = bucket_members(pop, tr, plan.buckets())
+    assert sorted(np.concatenate(members).tolist()) == list(range(pop.P))
+    for i, (bk, m) in enumerate(zip(plan.buckets(), members)):
+        m = m[st[m] == 0]
+        err = np.abs(Y[m] - ref[m])
+        bad = err > RTOL * cond[m] + ABS_FLOOR
+        assert not bad.any(), (i, int(bad.sum()))
+        pos = cond[m] > 0
+        worst = float((err[pos] / cond[m][pos]).max()) if pos.any() else 0.0
+        print(f"bucket {i} engine {bk['engine']} rows<={bk['rows_class']} "
+              f"{len(m)} genomes: worst |err|/cond {worst:.3e}")
 
 
 def test_buckets_one_by_one_rebuild_the_outputs():
