@@ -20,6 +20,8 @@ It is the plain, slow definition of what the method computes, in float64
                  to connection weights and node biases.
 * ``hyperneat``- CPPN queries over a grid substrate and the substrate forward
                  (HyperNEAT, named in Section 4.4).
+* ``reproduce`` - crossover and mutation as tensorized row operations
+                 (Section 3.2; hyperparameters of Appendices A and C).
 
 Every place where the paper is silent takes one stated reading; each function's
 docstring names it.
@@ -36,3 +38,4 @@ from .inference import (  # noqa: F401
 from .compat import genome_genes, distance, distance_matrix  # noqa: F401
 from .adjoint import backward, backward_population  # noqa: F401
 from . import hyperneat  # noqa: F401
+from . import reproduce  # noqa: F401

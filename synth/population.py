@@ -526,3 +526,12 @@ def to_paper_layout(pop: Population):
     for j, a in enumerate((pop.conn_in, pop.conn_out, pop.conn_en, pop.conn_w)):
         PC[..., j] = np.where(cv, a.astype(np.float32), np.float32(np.nan))
     return PN, PC
+
+
+def reproduction_draws(n_children: int, n_uniform: int, n_normal: int, seed: int):
+    """Random draws consumed by crossover and mutation, as inputs: uniforms in
+    [0, 1) [n][n_uniform] and standard normals [n][n_normal], float32."""
+    rng = np.random.default_rng(seed)
+    U = rng.random((n_children, n_uniform), dtype=np.float32)
+    Z = rng.standard_normal((n_children, n_normal), dtype=np.float32)
+    return U, Z
