@@ -15,7 +15,8 @@ It is the plain, slow definition of what the method computes, in float64
                  topological order, f_c = w * input, f_n = act(agg(.) + b),
                  plus the XOR fitness and MSE loss epilogues.
 * ``compat``   - the speciation compatibility distance over connection genes
-                 aligned by historical marking (Section 2.1, Appendix A).
+                 aligned by historical marking (Section 2.1, Appendix A), and
+                 the node-inclusive form with the paper's coefficient pair.
 * ``adjoint``  - reverse-mode derivative of the calculation stage with respect
                  to connection weights and node biases.
 * ``hyperneat``- CPPN queries over a grid substrate and the substrate forward
@@ -35,7 +36,9 @@ from .inference import (  # noqa: F401
     activate, activation_slope, aggregate, forward, forward_population,
     xor_fitness, sse_loss,
 )
-from .compat import genome_genes, distance, distance_matrix  # noqa: F401
+from .compat import (  # noqa: F401
+    genome_genes, distance, distance_matrix, node_genes, distance_nodes, distance_nodes_matrix,
+)
 from .adjoint import backward, backward_population  # noqa: F401
 from . import hyperneat  # noqa: F401
 from . import reproduce  # noqa: F401
