@@ -585,6 +585,32 @@ int tn_distance(const tn_population* pop, float c1, float c2, float c3,
                 void* workspace, float* dist, int32_t* excess, int32_t* disjoint,
                 hipStream_t stream);
 
+/*
+ * tn_distance without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, results (bit for bit) and kernels as
+ * tn_distance, except that the workspace is a fixed device array inside the
+ * library, TN_DISTANCE_NOALLOC_SCRATCH_BYTES large on every device the
+ * library runs on (held until the process ends). The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *
+ * Limit: a population whose workspace (tn_distance_workspace_size) exceeds
+ * TN_DISTANCE_NOALLOC_SCRATCH_BYTES returns TN_EUNSUPPORTED and launches
+ * nothing (16 MiB hold, e.g., 4096 genomes at C_max 256 or 1000 at C_max
+ * 1024).
+ *
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (on two streams, or from two host threads without ordering)
+ * race and their results are undefined. Calls ordered on one stream are safe;
+ * each call rewrites every entry it later reads, so nothing carries over
+ * from the previous call.
+ */
+#define TN_DISTANCE_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+int tn_distance_noalloc(const tn_population* pop, float c1, float c2, float c3,
+                        float* dist, int32_t* excess, int32_t* disjoint,
+                        hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,9 @@ SIGNATURES = {
     "tn_distance_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(ctypes.c_size_t)]),
     "tn_distance": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_void_p, c_float_p, c_int32_p, c_int32_p, _STREAM]),
+    "tn_distance_noalloc": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, c_float_p, c_int32_p, c_int32_p,
+                                           _STREAM]),
     "tn_plan_create": (ctypes.c_int, [_POP, _TR, ctypes.c_int32, ctypes.c_char_p,
                                       ctypes.POINTER(ctypes.c_void_p), _STREAM]),
     "tn_plan_destroy": (None, [ctypes.c_void_p]),

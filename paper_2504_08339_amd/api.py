@@ -303,10 +303,7 @@ class DistanceWorkspace:
         self.buf = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=pop.device)
 
 
-def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
-             counts: bool = True, workspace: Optional[DistanceWorkspace] = None, out=None):
-    """(dist [P][P], excess [P][P] or None, disjoint [P][P] or None)."""
-    ws = workspace if workspace is not None else DistanceWorkspace(pop)
+def _distance_outputs(pop: Population, counts: bool, out):
     P = pop.P
     if out is None:
         dist = torch.empty((P, P), dtype=torch.float32, device=pop.device)
@@ -320,12 +317,32 @@ def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
         if E is not None:
             _need(E, "excess", torch.int32, (P, P), pop.device)
             _need(D, "disjoint", torch.int32, (P, P), pop.device)
+    return dist, E, D
+
+
+def distance(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
+             counts: bool = True, workspace: Optional[DistanceWorkspace] = None, out=None):
+    """(dist [P][P], excess [P][P] or None, disjoint [P][P] or None)."""
+    ws = workspace if workspace is not None else DistanceWorkspace(pop)
+    dist, E, D = _distance_outputs(pop, counts, out)
     if ws.buf.device != pop.device or ws.buf.numel() < ws.nbytes:
         raise ValueError("distance workspace from another population or device")
     _check("tn_distance", _lib.tn_distance(
         ctypes.byref(pop.c), c1, c2, c3, ctypes.c_void_p(ws.buf.data_ptr()),
         _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p), _p(D, _abi.c_int32_p),
         _stream(pop.device)))
+    return dist, E, D
+
+
+def distance_noalloc(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: float = 0.4,
+                     counts: bool = True, out=None):
+    """distance() through tn_distance_noalloc: the library's fixed device scratch
+    instead of a workspace (no device allocation by the call; pass ``out`` to
+    allocate nothing here either)."""
+    dist, E, D = _distance_outputs(pop, counts, out)
+    _check("tn_distance_noalloc", _lib.tn_distance_noalloc(
+        ctypes.byref(pop.c), c1, c2, c3, _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p),
+        _p(D, _abi.c_int32_p), _stream(pop.device)))
     return dist, E, D
 
 

@@ -38,6 +38,7 @@ int launch_pack(const float* PN, const float* PC, int P, int N_max, int C_max,
 size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
+int noalloc_scratch(void** out);
 
 size_t max_dynamic_lds() {
   static size_t cached = 0;
@@ -337,6 +338,22 @@ int tn_distance(const tn_population* pop, float c1, float c2, float c3, void* wo
   if (pop->P == 0) return TN_OK;
   if (!workspace || !dist) return TN_EINVAL;
   return launch_distance(*pop, c1, c2, c3, workspace, dist, excess, disjoint, stream);
+}
+
+int tn_distance_noalloc(const tn_population* pop, float c1, float c2, float c3, float* dist,
+                        int32_t* excess, int32_t* disjoint, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if ((excess == nullptr) != (disjoint == nullptr)) return TN_EINVAL;
+  if (pop->P > 65535) return TN_EUNSUPPORTED;
+  if (pop->P == 0) return TN_OK;
+  if (!dist) return TN_EINVAL;
+  if (distance_workspace_bytes(pop->P, pop->C_max) > (size_t)TN_DISTANCE_NOALLOC_SCRATCH_BYTES)
+    return TN_EUNSUPPORTED;
+  void* ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc != TN_OK) return rc;
+  return launch_distance(*pop, c1, c2, c3, ws, dist, excess, disjoint, stream);
 }
 
 int tn_cppn_query(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,

@@ -12,6 +12,7 @@
 //         and probed against every row; only the pairs on or above the
 //         diagonal are evaluated, each written to both halves.
 #include <algorithm>
+#include <mutex>
 
 #include "tn_internal.hpp"
 
@@ -274,6 +275,39 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
 }  // namespace
 
 size_t distance_workspace_bytes(int P, int C_max) { return ws_bytes(P, C_max); }
+
+// ------------------------------------------------ allocation-free variant
+
+// Workspace of tn_distance_noalloc: a fixed device array instead of a caller
+// buffer. Each device holds its own copy for the life of the process; every
+// call on a device reuses it (the prep kernel rewrites every entry the pair
+// kernel reads, so nothing needs clearing between calls).
+static __device__ __align__(256) unsigned char scratch[TN_DISTANCE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (host code must never use the array's name as an address).
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  int rc = record_hip(hipGetDevice(&dev));
+  if (rc != TN_OK) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return TN_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    rc = record_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (rc != TN_OK) return rc;
+    if (!ptr) return record_hip(hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TN_OK;
+}
 
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream) {
