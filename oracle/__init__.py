@@ -21,6 +21,9 @@ It is the plain, slow definition of what the method computes, in float64
                  to connection weights and node biases.
 * ``hyperneat``- CPPN queries over a grid substrate and the substrate forward
                  (HyperNEAT, named in Section 4.4).
+* ``recurrent`` - forward pass of recurrent networks by synchronous sweeps
+                 (network type of Appendix A; Section 3.3 covers only the
+                 feedforward calculation).
 * ``reproduce`` - crossover and mutation as tensorized row operations
                  (Section 3.2; hyperparameters of Appendices A and C).
 
@@ -42,3 +45,4 @@ from .compat import (  # noqa: F401
 from .adjoint import backward, backward_population  # noqa: F401
 from . import hyperneat  # noqa: F401
 from . import reproduce  # noqa: F401
+from .recurrent import recurrent_forward, recurrent_population, recurrent_status  # noqa: F401
