@@ -88,12 +88,15 @@ def activation_slope(name: str, z: np.ndarray, r: np.ndarray) -> np.ndarray:
         return (z + r > 0.0).astype(np.float64)
     lo = np.maximum(np.abs(z) - r, 0.0)          # smallest |zeta| in the interval
     hi = np.abs(z) + r                           # largest |zeta|
+    # both slopes peak at 0 and fall with |zeta|; written without 1 - s
+    # (which rounds to 0 once s rounds to 1, from |zeta| of about 19 for tanh
+    # and 37 for sigmoid, while the true slope is still positive)
     if name == "tanh":
-        t = np.tanh(lo)
-        return 1.0 - t * t
+        e = np.exp(-2.0 * lo)
+        return 4.0 * e / ((1.0 + e) * (1.0 + e))
     if name == "sigmoid":
-        s = 1.0 / (1.0 + np.exp(-lo))
-        return s * (1.0 - s)
+        e = np.exp(-lo)
+        return e / ((1.0 + e) * (1.0 + e))
     if name == "sin":
         k_lo = np.ceil((z - r) / math.pi)
         k_hi = np.floor((z + r) / math.pi)

@@ -174,3 +174,22 @@ def test_planted_wrong_source(monkeypatch):
                                   for e in edges]
         return tr
     assert _mlp_pin_fails(monkeypatch, lambda m: m.setattr(of, "transform", shifted))
+
+
+@pytest.mark.parametrize("name", ["sigmoid", "tanh"])
+def test_activation_slope_bound_far_out(name):
+    """The error-scale slope bound of sigmoid and tanh equals the largest |act'|
+    over the interval, also far from 0 where act' is tiny but positive;
+    references: exp(log_expit(x) + log_expit(-x)) (SciPy) and 1 / cosh(x)^2."""
+    from scipy.special import log_expit
+    ref = {"sigmoid": lambda x: np.exp(log_expit(x) + log_expit(-x)),
+           "tanh": lambda x: 1.0 / np.cosh(x) ** 2}[name]
+    from oracle.inference import activation_slope
+    for z in np.linspace(-60.0, 60.0, 97):
+        for r in (0.0, 0.1, 5.0):
+            bound = float(activation_slope(name, np.array(z), np.array(r)))
+            grid = np.linspace(z - r, z + r, 201)
+            brute = float(ref(grid).max())
+            assert bound >= brute * (1 - 1e-9), (z, r, bound, brute)
+            assert bound <= ref(max(abs(z) - r, 0.0)) * (1 + 1e-9), (z, r)
+            assert bound > 0.0
