@@ -369,6 +369,31 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr,
                     float scale, float offset, float* out, float* loss,
                     hipStream_t stream);
 
+/*
+ * Forward pass of RECURRENT networks (network type "recurrent" of Appendix A:
+ * enabled connections may form cycles, including self-loops). The paper
+ * details the calculation only for feedforward networks (Section 3.3); here a
+ * recurrent network is evaluated by T synchronous sweeps:
+ *   v_0[input i] = x[i], v_0[k] = 0 for every other node;
+ *   sweep t = 1..T: v_t[k] = act_k(bias_k + resp_k * agg_k(w_e * v_{t-1}[src_e]))
+ *     for every non-input node k over its enabled in-edges (ascending
+ *     connection row), all from the previous sweep; inputs keep their values;
+ *   y[j] = v_T[output key n_in + j]  (T = 0: all outputs 0).
+ * Sum aggregation accumulates with fused multiply-add in ascending in-edge
+ * order and z = fma(resp, aggregate, bias), as tn_forward does, so an acyclic
+ * sum-aggregation genome gives tn_forward's bits once T exceeds its largest
+ * topological level.
+ *
+ * obs, obs_genome_stride, B and out as in tn_forward; T >= 0 sweeps.
+ * status (may be NULL): device int32 [P], the tn_genome_status bits of each
+ * genome with TN_CYCLE never set (cycles are allowed); a genome with any bit
+ * gets NaN outputs. The whole genome's values sit in LDS: TN_EUNSUPPORTED when
+ * 2 * N_max * 64 floats plus its tables exceed one workgroup's LDS (N_max up
+ * to about 280 at C_max 256 on MI355X).
+ */
+int tn_forward_recurrent(const tn_population* pop, const float* obs, int64_t obs_genome_stride,
+                         int32_t B, int32_t T, float* out, int32_t* status, hipStream_t stream);
+
 /* ------------------------------------------------------- batched plan */
 
 /*
@@ -610,6 +635,135 @@ int tn_distance(const tn_population* pop, float c1, float c2, float c3,
 int tn_distance_noalloc(const tn_population* pop, float c1, float c2, float c3,
                         float* dist, int32_t* excess, int32_t* disjoint,
                         hipStream_t stream);
+
+/*
+ * Node-inclusive compatibility distance with the coefficient pair the paper
+ * lists for its own speciation (Appendix A: compatibility_disjoint c_d and
+ * compatibility_homologous c_h; Section 5.2 states that this distance is not
+ * NEAT-Python's, and the paper prints no formula). Reading implemented here,
+ * over node genes and connection genes alike:
+ *   delta = delta_nodes + delta_conns
+ *   delta_X = (c_d * D_X + c_h * H_X) / max(|X1|, |X2|)   (0 if both are empty)
+ * Node genes are the valid non-input node rows, identified by key; connection
+ * genes are the valid connection rows, enabled or not, identified by the
+ * marking (in-key, out-key). D_X counts the genes only one of the two genomes
+ * holds. H_X sums over the genes both hold, in ascending key / marking order,
+ *   |bias1 - bias2| + |resp1 - resp2| + [act1 != act2] + [agg1 != agg2]  (nodes)
+ *   |w1 - w2| + [enabled1 != enabled2]                                    (connections)
+ * in float32. The matrix is symmetric bit for bit and its diagonal is 0. A
+ * genome with a repeated node key or marking, or a ragged genome above
+ * N_max / C_max, has no gene set: its distances are NaN and its counts -1.
+ *
+ *   workspace  device buffer of tn_distance_nodes_workspace_size() bytes
+ *   dist       [P][P] float32
+ *   d_nodes, d_conns  [P][P] int32 (D_nodes, D_conns), may be NULL (both or neither)
+ * P <= 65535 (TN_EUNSUPPORTED above).
+ */
+int tn_distance_nodes_workspace_size(const tn_population* pop, size_t* bytes);
+
+int tn_distance_nodes(const tn_population* pop, float c_disjoint, float c_homologous,
+                      void* workspace, float* dist, int32_t* d_nodes, int32_t* d_conns,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------- reproduction */
+
+/*
+ * Crossover and mutation of a padded population as the paper's tensorized row
+ * operations (Section 3.2: a node or connection is added in the first empty
+ * row, removed by emptying its row, and its attributes are changed in place;
+ * the hyperparameters are those of Appendix A, defaults in Appendix C). The
+ * random draws are inputs: the children are a pure function of the parents
+ * and the draws. Per child c, with parents a = parents[c][0] (the fitter one)
+ * and b = parents[c][1]:
+ *
+ *  1. Crossover (NEAT's alignment by historical marking, Section 2.1): the
+ *     child takes a's rows in a's positions. A node row of a whose key b also
+ *     holds, and a connection row whose marking (in-key, out-key) b also
+ *     holds, takes b's attributes (bias, response, act, agg; weight, enabled)
+ *     when its coin is below 1/2 (b's first row with that key / marking).
+ *     Genes only b holds are not inherited.
+ *  2. Add node (draw below node_add): an enabled connection x -> y is picked
+ *     and disabled; a new node takes the first empty node row with the key the
+ *     call's innovation table gives (x, y), bias and response drawn from their
+ *     initial distributions, act_default / agg_default; x -> new (weight 1) and
+ *     new -> y (the old weight), enabled, take the first two empty connection
+ *     rows. Skipped when no enabled connection, node row or two connection
+ *     rows are free.
+ *  3. Delete node (node_delete): a hidden node row is emptied with every
+ *     connection row naming its key.
+ *  4. Add connection (conn_add): a source among the input and hidden node rows
+ *     and a destination among the hidden and output node rows are picked; the
+ *     connection takes the first empty row, enabled, weight from its initial
+ *     distribution, unless source = destination, the marking is present
+ *     (enabled or not), no row is free, or (allow_cycles = 0) the destination
+ *     reaches the source over valid connections.
+ *  5. Delete connection (conn_delete): a valid connection row is emptied.
+ *  6. Attributes of every valid non-input node row and valid connection row:
+ *     a float attribute v with uniform u and normal z becomes v + power*z when
+ *     u < mutate_rate, init_mean + init_std*z when u < mutate_rate +
+ *     replace_rate, else stays; an act (agg) code is replaced, when its draw
+ *     is below act_replace_rate (agg_replace_rate), by option
+ *     floor(u2 * n_options) of the ascending option list.
+ * "Picked" = candidate rows in ascending row order, index floor(u * n) (the
+ * product rounded to float32), at most n - 1. Every float update rounds each
+ * product and sum to float32 on its own (no fused multiply-add).
+ *
+ * Draws per child (tn_reproduce_draws gives the counts): uniforms U [n][nU]
+ *   U[0..8]  add node: decision, pick; delete node: decision, pick; add
+ *            connection: decision, source pick, destination pick; delete
+ *            connection: decision, pick (U[9..15] unused)
+ *   U[16 + r]                  crossover coin of node row r
+ *   U[16 + N_max + r]          crossover coin of connection row r
+ *   U[16 + N_max + C_max + 6r + k]  node row r: bias, response, act decision,
+ *                              act pick, agg decision, agg pick
+ *   U[16 + 7 N_max + C_max + r]     connection row r weight
+ * normals Z [n][nZ]: Z[0] new node bias, Z[1] new node response, Z[2] new
+ *   connection weight, Z[4 + 2r + k] node row r bias (k = 0) / response (1),
+ *   Z[4 + 2 N_max + r] connection row r weight.
+ *
+ * Innovation table of one call: the distinct split markings among the
+ * children get keys next_key + their rank in lexicographic order (one split
+ * done by several children gives them one key); next_key must exceed every key
+ * in the parents and next_key + n must stay below 2^31 (neither is checked).
+ * *next_key_out (device int32) receives the next unused key.
+ *
+ *   pop        padded parent population (ragged: TN_EUNSUPPORTED)
+ *   parents    device int32 [n][2]. A first parent outside [0, P) gives an
+ *              all-empty child; a second parent outside [0, P) (e.g. -1) makes
+ *              the child an unchanged copy of the first (an elite).
+ *   U, Z       device float32 as above
+ *   children   device arrays [n][N_max] / [n][C_max] (same capacities as pop);
+ *              must not overlap the parents' arrays
+ *   workspace  tn_reproduce_workspace_size(n) bytes of device memory
+ * TN_EINVAL for null pointers, n < 0, probabilities outside [0, 1], an option
+ * list that is empty, longer than 8 or not strictly ascending, or a default
+ * code above 255; TN_EUNSUPPORTED when N_max / C_max exceed what one
+ * workgroup's LDS holds.
+ */
+typedef struct tn_mutation_params {
+    float node_add, node_delete, conn_add, conn_delete;
+    float bias_init_mean, bias_init_std, bias_mutate_power, bias_mutate_rate, bias_replace_rate;
+    float resp_init_mean, resp_init_std, resp_mutate_power, resp_mutate_rate, resp_replace_rate;
+    float weight_init_mean, weight_init_std, weight_mutate_power, weight_mutate_rate,
+          weight_replace_rate;
+    float act_replace_rate, agg_replace_rate;
+    int32_t act_default, agg_default;
+    int32_t n_act_options, n_agg_options;
+    uint8_t act_options[8];   /* ascending activation codes */
+    uint8_t agg_options[8];   /* ascending aggregation codes */
+    int32_t allow_cycles;     /* 0: feedforward genomes (cycle check on add connection) */
+} tn_mutation_params;
+
+/* Draw counts per child: *n_uniform = 16 + 7 N_max + 2 C_max,
+ * *n_normal = 4 + 2 N_max + C_max. Host only. */
+int tn_reproduce_draws(int32_t N_max, int32_t C_max, int32_t* n_uniform, int32_t* n_normal);
+
+int tn_reproduce_workspace_size(int32_t n_children, size_t* bytes);
+
+int tn_reproduce(const tn_population* pop, int32_t n_children, const int32_t* parents,
+                 const float* U, const float* Z, const tn_mutation_params* params,
+                 int32_t next_key, const tn_population_arrays* children, int32_t* next_key_out,
+                 void* workspace, hipStream_t stream);
 
 #ifdef __cplusplus
 }

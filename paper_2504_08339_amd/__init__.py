@@ -12,6 +12,7 @@ from ._abi import (  # noqa: F401
 from .api import (  # noqa: F401
     Population, Transformed, DistanceWorkspace, transform, forward, forward_loss, distance, lib,
     backward, forward_backward_mse, Plan, cppn_query, substrate_forward,
-    substrate_backward, cppn_backward, pack_paper_layout, distance_noalloc,
+    substrate_backward, cppn_backward, pack_paper_layout, distance_noalloc, distance_nodes,
+    MutationParams, reproduce, reproduce_draws, forward_recurrent,
 )
 from .autograd import TNForward  # noqa: F401

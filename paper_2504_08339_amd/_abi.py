@@ -70,6 +70,20 @@ class TnSubstrate(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("n_out", ctypes.c_int32), ("threshold", ctypes.c_float)]
 
 
+class TnMutationParams(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_float) for n in (
+        "node_add", "node_delete", "conn_add", "conn_delete",
+        "bias_init_mean", "bias_init_std", "bias_mutate_power", "bias_mutate_rate",
+        "bias_replace_rate", "resp_init_mean", "resp_init_std", "resp_mutate_power",
+        "resp_mutate_rate", "resp_replace_rate", "weight_init_mean", "weight_init_std",
+        "weight_mutate_power", "weight_mutate_rate", "weight_replace_rate",
+        "act_replace_rate", "agg_replace_rate")] +
+        [(n, ctypes.c_int32) for n in ("act_default", "agg_default", "n_act_options",
+                                       "n_agg_options")] +
+        [("act_options", ctypes.c_uint8 * 8), ("agg_options", ctypes.c_uint8 * 8),
+         ("allow_cycles", ctypes.c_int32)])
+
+
 class TnBucketInfo(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("rows_class", ctypes.c_int32),
                 ("count", ctypes.c_int32), ("edges", ctypes.c_int64), ("tile", TnTile)]
@@ -108,6 +122,18 @@ SIGNATURES = {
     "tn_distance_noalloc": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float,
                                            ctypes.c_float, c_float_p, c_int32_p, c_int32_p,
                                            _STREAM]),
+    "tn_distance_nodes_workspace_size": (ctypes.c_int, [_POP, ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_distance_nodes": (ctypes.c_int, [_POP, ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                         c_float_p, c_int32_p, c_int32_p, _STREAM]),
+    "tn_reproduce_draws": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, c_int32_p, c_int32_p]),
+    "tn_reproduce_workspace_size": (ctypes.c_int, [ctypes.c_int32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_reproduce": (ctypes.c_int, [_POP, ctypes.c_int32, c_int32_p, c_float_p, c_float_p,
+                                    ctypes.POINTER(TnMutationParams), ctypes.c_int32,
+                                    ctypes.POINTER(TnPopulationArrays), c_int32_p,
+                                    ctypes.c_void_p, _STREAM]),
+    "tn_forward_recurrent": (ctypes.c_int, [_POP, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_int32, c_float_p, c_int32_p, _STREAM]),
     "tn_plan_create": (ctypes.c_int, [_POP, _TR, ctypes.c_int32, ctypes.c_char_p,
                                       ctypes.POINTER(ctypes.c_void_p), _STREAM]),
     "tn_plan_destroy": (None, [ctypes.c_void_p]),

@@ -7,7 +7,8 @@ TNError on a non-zero status. No arithmetic of the method happens here.
 from __future__ import annotations
 
 import ctypes
-from typing import Optional
+import dataclasses
+from typing import Optional, Tuple
 
 import numpy as np
 import torch
@@ -246,6 +247,20 @@ def forward(pop: Population, tr: Transformed, obs: torch.Tensor,
     return out
 
 
+def forward_recurrent(pop: Population, obs: torch.Tensor, T: int,
+                      out: Optional[torch.Tensor] = None, with_status: bool = False):
+    """Outputs [P][B][n_out] of recurrent networks after T synchronous sweeps
+    (tn_forward_recurrent; no transformation needed). With ``with_status`` also
+    the per-genome status bits [P] (cycles allowed)."""
+    B, stride = _obs_stride(pop, obs)
+    out = _out(pop, out, B)
+    status = torch.empty(max(pop.P, 1), dtype=torch.int32, device=pop.device) if with_status else None
+    _check("tn_forward_recurrent", _lib.tn_forward_recurrent(
+        ctypes.byref(pop.c), _p(obs, _abi.c_float_p), stride, B, int(T), _p(out, _abi.c_float_p),
+        _p(status, _abi.c_int32_p), _stream(pop.device)))
+    return (out, status[:pop.P]) if with_status else out
+
+
 def forward_loss(pop: Population, tr: Transformed, obs: torch.Tensor, target: torch.Tensor,
                  scale: float = 1.0, offset: float = 0.0, store_outputs: bool = True):
     """(loss [P], outputs or None): loss[g] = offset + scale * sum (y - target)^2."""
@@ -344,6 +359,115 @@ def distance_noalloc(pop: Population, c1: float = 1.0, c2: float = 1.0, c3: floa
         ctypes.byref(pop.c), c1, c2, c3, _p(dist, _abi.c_float_p), _p(E, _abi.c_int32_p),
         _p(D, _abi.c_int32_p), _stream(pop.device)))
     return dist, E, D
+
+
+def distance_nodes(pop: Population, c_disjoint: float = 1.0, c_homologous: float = 0.5,
+                   counts: bool = True, out=None):
+    """(dist [P][P], D_nodes [P][P] or None, D_conns [P][P] or None): the
+    node-inclusive distance of tn_distance_nodes."""
+    n = ctypes.c_size_t()
+    _check("tn_distance_nodes_workspace_size",
+           _lib.tn_distance_nodes_workspace_size(ctypes.byref(pop.c), ctypes.byref(n)))
+    ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=pop.device)
+    dist, DN, DC = _distance_outputs(pop, counts, out)
+    _check("tn_distance_nodes", _lib.tn_distance_nodes(
+        ctypes.byref(pop.c), c_disjoint, c_homologous, ctypes.c_void_p(ws.data_ptr()),
+        _p(dist, _abi.c_float_p), _p(DN, _abi.c_int32_p), _p(DC, _abi.c_int32_p),
+        _stream(pop.device)))
+    return dist, DN, DC
+
+
+@dataclasses.dataclass
+class MutationParams:
+    """Reproduction hyperparameters (Appendix A; defaults of Appendix C's
+    feedforward setting: tanh hidden nodes, sum aggregation)."""
+    node_add: float = 0.2
+    node_delete: float = 0.0
+    conn_add: float = 0.4
+    conn_delete: float = 0.0
+    bias_init_mean: float = 0.0
+    bias_init_std: float = 1.0
+    bias_mutate_power: float = 0.5
+    bias_mutate_rate: float = 0.7
+    bias_replace_rate: float = 0.1
+    resp_init_mean: float = 1.0
+    resp_init_std: float = 0.0
+    resp_mutate_power: float = 0.0
+    resp_mutate_rate: float = 0.0
+    resp_replace_rate: float = 0.0
+    weight_init_mean: float = 0.0
+    weight_init_std: float = 1.0
+    weight_mutate_power: float = 0.5
+    weight_mutate_rate: float = 0.8
+    weight_replace_rate: float = 0.1
+    act_default: int = 2
+    agg_default: int = 0
+    act_replace_rate: float = 0.0
+    agg_replace_rate: float = 0.0
+    act_options: Tuple[int, ...] = (2,)
+    agg_options: Tuple[int, ...] = (0,)
+    allow_cycles: bool = False
+
+    def to_c(self) -> "_abi.TnMutationParams":
+        c = _abi.TnMutationParams()
+        for f in dataclasses.fields(self):
+            if f.name in ("act_options", "agg_options"):
+                opts = sorted(int(o) for o in getattr(self, f.name))
+                if not 1 <= len(opts) <= 8:
+                    raise ValueError(f"{f.name}: 1 to 8 codes")
+                arr = getattr(c, f.name)
+                for i, o in enumerate(opts):
+                    arr[i] = o
+                setattr(c, "n_" + f.name, len(opts))
+            elif f.name == "allow_cycles":
+                c.allow_cycles = int(bool(self.allow_cycles))
+            else:
+                setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+def reproduce_draws(N_max: int, C_max: int):
+    """(uniforms, normals) tn_reproduce reads per child."""
+    nu, nz = ctypes.c_int32(), ctypes.c_int32()
+    _check("tn_reproduce_draws", _lib.tn_reproduce_draws(N_max, C_max, ctypes.byref(nu),
+                                                          ctypes.byref(nz)))
+    return int(nu.value), int(nz.value)
+
+
+def reproduce(pop: Population, parents: torch.Tensor, U: torch.Tensor, Z: torch.Tensor,
+              params: Optional[MutationParams] = None, next_key: int = 0):
+    """Children of a padded population by crossover and mutation (tn_reproduce):
+    parents int32 [n][2] (fitter first; a second parent of -1 copies the first),
+    draws U [n][n_uniform], Z [n][n_normal] float32. Returns (children as a
+    Population with the parents' capacities, next unused key as a device int32
+    tensor [1])."""
+    if pop.ragged:
+        raise ValueError("reproduce takes a padded population")
+    d = pop.device
+    if not isinstance(parents, torch.Tensor) or parents.dim() != 2:
+        raise ValueError("parents must be an int32 [n][2] tensor")
+    n = parents.shape[0]
+    nu, nz = reproduce_draws(pop.N_max, pop.C_max)
+    _need(parents, "parents", torch.int32, (n, 2), d)
+    _need(U, "U", torch.float32, (n, nu), d)
+    _need(Z, "Z", torch.float32, (n, nz), d)
+    prm = (params or MutationParams()).to_c()
+    ts = {k: torch.empty((n, pop.N_max), dtype=dt, device=d) for k, dt in _NODE.items()}
+    ts.update({k: torch.empty((n, pop.C_max), dtype=dt, device=d) for k, dt in _CONN.items()})
+    arrays = _abi.TnPopulationArrays(*[_p(ts[k], ty) for k, ty in (
+        ("node_key", _abi.c_int32_p), ("node_bias", _abi.c_float_p),
+        ("node_resp", _abi.c_float_p), ("node_act", _abi.c_uint8_p),
+        ("node_agg", _abi.c_uint8_p), ("conn_in", _abi.c_int32_p), ("conn_out", _abi.c_int32_p),
+        ("conn_w", _abi.c_float_p), ("conn_en", _abi.c_uint8_p))])
+    nb = ctypes.c_size_t()
+    _check("tn_reproduce_workspace_size", _lib.tn_reproduce_workspace_size(n, ctypes.byref(nb)))
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=d)
+    nk = torch.empty(1, dtype=torch.int32, device=d)
+    _check("tn_reproduce", _lib.tn_reproduce(
+        ctypes.byref(pop.c), n, _p(parents, _abi.c_int32_p), _p(U, _abi.c_float_p),
+        _p(Z, _abi.c_float_p), ctypes.byref(prm), int(next_key), ctypes.byref(arrays),
+        _p(nk, _abi.c_int32_p), ctypes.c_void_p(ws.data_ptr()), _stream(d)))
+    return Population(pop.n_in, pop.n_out, pop.N_max, pop.C_max, ts), nk
 
 
 class Plan:

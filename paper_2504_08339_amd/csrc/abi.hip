@@ -39,6 +39,17 @@ size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
 int noalloc_scratch(void** out);
+int recurrent_lds_check(const tn_population& p, size_t* bytes);
+int launch_forward_recurrent(const tn_population& p, const float* obs, int64_t obs_stride, int B,
+                             int T, float* out, int32_t* status, hipStream_t stream);
+size_t reproduce_workspace_bytes(int n);
+int launch_reproduce(const tn_population& p, int n, const int32_t* parents, const float* U,
+                     const float* Z, const tn_mutation_params& prm, int32_t next_key,
+                     const tn_population_arrays& out, int32_t* next_key_out, void* workspace,
+                     hipStream_t stream);
+size_t distance_nodes_workspace_bytes(int P, int N_max, int C_max);
+int launch_distance_nodes(const tn_population& p, float c_d, float c_h, void* workspace,
+                          float* dist, int32_t* DN, int32_t* DC, hipStream_t stream);
 
 size_t max_dynamic_lds() {
   static size_t cached = 0;
@@ -354,6 +365,105 @@ int tn_distance_noalloc(const tn_population* pop, float c1, float c2, float c3, 
   rc = noalloc_scratch(&ws);
   if (rc != TN_OK) return rc;
   return launch_distance(*pop, c1, c2, c3, ws, dist, excess, disjoint, stream);
+}
+
+int tn_distance_nodes_workspace_size(const tn_population* pop, size_t* bytes) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (!bytes) return TN_EINVAL;
+  *bytes = distance_nodes_workspace_bytes(pop->P, pop->N_max, pop->C_max);
+  return TN_OK;
+}
+
+int tn_distance_nodes(const tn_population* pop, float c_disjoint, float c_homologous,
+                      void* workspace, float* dist, int32_t* d_nodes, int32_t* d_conns,
+                      hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if ((d_nodes == nullptr) != (d_conns == nullptr)) return TN_EINVAL;
+  if (pop->P > 65535) return TN_EUNSUPPORTED;
+  if (pop->P == 0) return TN_OK;
+  if (!workspace || !dist) return TN_EINVAL;
+  return launch_distance_nodes(*pop, c_disjoint, c_homologous, workspace, dist, d_nodes, d_conns,
+                               stream);
+}
+
+int tn_reproduce_draws(int32_t N_max, int32_t C_max, int32_t* n_uniform, int32_t* n_normal) {
+  if (!n_uniform || !n_normal || N_max < 1 || C_max < 1) return TN_EINVAL;
+  if (N_max > TN_MAX_NODES || C_max > TN_MAX_CONNS) return TN_EUNSUPPORTED;
+  *n_uniform = 16 + 7 * N_max + 2 * C_max;
+  *n_normal = 4 + 2 * N_max + C_max;
+  return TN_OK;
+}
+
+int tn_reproduce_workspace_size(int32_t n_children, size_t* bytes) {
+  if (!bytes || n_children < 0) return TN_EINVAL;
+  *bytes = reproduce_workspace_bytes(n_children);
+  return TN_OK;
+}
+
+namespace {
+bool prob_ok(float p) { return p >= 0.0f && p <= 1.0f; }  // false for NaN
+
+bool options_ok(int32_t n, const uint8_t* o) {
+  if (n < 1 || n > 8) return false;
+  for (int i = 1; i < n; ++i)
+    if (o[i] <= o[i - 1]) return false;
+  return true;
+}
+
+int check_params(const tn_mutation_params* m) {
+  if (!m) return TN_EINVAL;
+  const float probs[] = {m->node_add, m->node_delete, m->conn_add, m->conn_delete,
+                         m->bias_mutate_rate, m->bias_replace_rate, m->resp_mutate_rate,
+                         m->resp_replace_rate, m->weight_mutate_rate, m->weight_replace_rate,
+                         m->act_replace_rate, m->agg_replace_rate};
+  for (float p : probs)
+    if (!prob_ok(p)) return TN_EINVAL;
+  if (!options_ok(m->n_act_options, m->act_options) ||
+      !options_ok(m->n_agg_options, m->agg_options))
+    return TN_EINVAL;
+  if (m->act_default < 0 || m->act_default > 255 || m->agg_default < 0 || m->agg_default > 255)
+    return TN_EINVAL;
+  return TN_OK;
+}
+}  // namespace
+
+int tn_reproduce(const tn_population* pop, int32_t n_children, const int32_t* parents,
+                 const float* U, const float* Z, const tn_mutation_params* params,
+                 int32_t next_key, const tn_population_arrays* children, int32_t* next_key_out,
+                 void* workspace, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->node_off) return TN_EUNSUPPORTED;
+  if (n_children < 0 || !next_key_out || !children) return TN_EINVAL;
+  rc = check_params(params);
+  if (rc != TN_OK) return rc;
+  if (n_children > 0) {
+    if (!parents || !U || !Z || !workspace) return TN_EINVAL;
+    const tn_population_arrays& o = *children;
+    if (!o.node_key || !o.node_bias || !o.node_resp || !o.node_act || !o.node_agg ||
+        !o.conn_in || !o.conn_out || !o.conn_w || !o.conn_en)
+      return TN_EINVAL;
+    if (pop->P == 0) return TN_EINVAL;  // children need parents
+  }
+  return launch_reproduce(*pop, n_children, parents, U, Z, *params, next_key, *children,
+                          next_key_out, workspace, stream);
+}
+
+int tn_forward_recurrent(const tn_population* pop, const float* obs, int64_t obs_genome_stride,
+                         int32_t B, int32_t T, float* out, int32_t* status, hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (T < 0) return TN_EINVAL;
+  rc = check_obs(pop, obs, obs_genome_stride, B);
+  if (rc != TN_OK) return rc;
+  if (pop->P == 0) return TN_OK;
+  if (B > 0 && !out) return TN_EINVAL;
+  size_t bytes = 0;
+  rc = recurrent_lds_check(*pop, &bytes);
+  if (rc != TN_OK) return rc;
+  return launch_forward_recurrent(*pop, obs, obs_genome_stride, B, T, out, status, stream);
 }
 
 int tn_cppn_query(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,

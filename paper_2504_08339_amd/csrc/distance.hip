@@ -272,6 +272,326 @@ __global__ __launch_bounds__(kPairBlock) void pair_kernel(Ws ws, int P, int HC, 
   }
 }
 
+
+// ------------------------------------------------ node-inclusive distance
+//
+// delta = sum over the two gene kinds X (node genes, connection genes) of
+//   (c_d * D_X + c_h * H_X) / max(|X1|, |X2|)          (0 when both are empty)
+// node genes: valid non-input node rows by key; connection genes: valid
+// connection rows (enabled or not) by marking. D_X counts the genes only one
+// genome holds; H_X sums, over the shared ones in ascending identity order,
+// |a0 - a0'| + |a1 - a1'| + [c0 != c0'] + [c1 != c1'] with (a0, a1, c0, c1) =
+// (bias, response, act, agg) for a node and (weight, 0, enabled, 0) for a
+// connection (the zero terms add exactly nothing).
+//
+// Same two-launch shape as the connection-gene distance: a prep wavefront per
+// genome sorts both gene lists (keys + the row they came from, bitonic in
+// LDS), checks repeated keys / markings, and stores them position-major with
+// their attributes; the pair kernel hashes R row genomes' genes in LDS and
+// walks each column genome's sorted lists once.
+
+struct GeneList {
+  long long* keyT;   // [cap][P]
+  int32_t* hT;       // [cap][P] hash_mark of the key
+  float* a0T;        // [cap][P]
+  float* a1T;        // [cap][P]
+  uint32_t* codeT;   // [cap][P] c0 | c1 << 8
+};
+
+struct WsN {
+  int32_t* cnt_n;    // [P] node genes, -1 for a genome without a gene set
+  int32_t* cnt_c;    // [P] connection genes, -1 likewise
+  GeneList nodes;    // cap N_max
+  GeneList conns;    // cap C_max
+};
+
+size_t gene_list_bytes(int P, int cap) {
+  const size_t n = (size_t)P * cap;
+  return align_up(sizeof(long long) * n) + 4 * align_up(4 * n);
+}
+
+GeneList carve_list(unsigned char* p, size_t& o, int P, int cap) {
+  const size_t n = (size_t)P * cap;
+  GeneList l;
+  l.keyT = (long long*)(p + o);
+  o += align_up(sizeof(long long) * n);
+  l.hT = (int32_t*)(p + o);
+  o += align_up(4 * n);
+  l.a0T = (float*)(p + o);
+  o += align_up(4 * n);
+  l.a1T = (float*)(p + o);
+  o += align_up(4 * n);
+  l.codeT = (uint32_t*)(p + o);
+  o += align_up(4 * n);
+  return l;
+}
+
+size_t ws_nodes_bytes(int P, int N, int C) {
+  return 2 * align_up(sizeof(int32_t) * P) + gene_list_bytes(P, N) + gene_list_bytes(P, C);
+}
+
+WsN carve_nodes(void* base, int P, int N, int C) {
+  unsigned char* p = (unsigned char*)base;
+  size_t o = 0;
+  WsN w;
+  w.cnt_n = (int32_t*)(p + o);
+  o += align_up(sizeof(int32_t) * P);
+  w.cnt_c = (int32_t*)(p + o);
+  o += align_up(sizeof(int32_t) * P);
+  w.nodes = carve_list(p, o, P, N);
+  w.conns = carve_list(p, o, P, C);
+  return w;
+}
+
+// Bitonic sort of S (a power of two) (key, row) pairs in LDS by key; one
+// wavefront.
+__device__ void wave_bitonic(long long* key, int32_t* row, int S) {
+  const int lane = lane_id();
+  for (int k = 2; k <= S; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < S; i += kWave) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const long long ki = key[i], kj = key[ixj];
+          if ((ki > kj) == ((i & k) == 0)) {
+            key[i] = kj;
+            key[ixj] = ki;
+            const int32_t t = row[i];
+            row[i] = row[ixj];
+            row[ixj] = t;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWave) void prep_nodes_kernel(PopView pop, WsN ws, int S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  long long* key = (long long*)smem;               // [S]
+  int32_t* row = (int32_t*)(smem + sizeof(long long) * S);  // [S]
+  const int g = blockIdx.x;
+  const int lane = lane_id();
+  const int P = pop.P;
+  const int64_t nb = pop.node_base(g), cb = pop.conn_base(g);
+  const int64_t nrows = pop.node_rows(g), crows = pop.conn_rows(g);
+  if (nrows > pop.N_max || nrows < 0 || crows > pop.C_max || crows < 0) {
+    if (lane == 0) {
+      ws.cnt_n[g] = -1;
+      ws.cnt_c[g] = -1;
+    }
+    return;
+  }
+  // node genes: every valid key is sorted (a repeated input key also leaves
+  // the genome without a gene set); the inputs, keys 0 .. n_in-1, come first
+  // and are skipped when storing
+  int n = 0;
+  for (int base = 0; base < (int)nrows; base += kWave) {
+    const int r = base + lane;
+    const int32_t k = r < nrows ? pop.node_key[nb + r] : -1;
+    const uint64_t m = __ballot(k >= 0);
+    if (k >= 0) {
+      key[n + mbcnt(m)] = (long long)k;
+      row[n + mbcnt(m)] = r;
+    }
+    n += __popcll(m);
+  }
+  for (int i = n + lane; i < S; i += kWave) {
+    key[i] = kPadKey;
+    row[i] = -1;
+  }
+  wave_sync();
+  wave_bitonic(key, row, S);
+  bool dup = false;
+  for (int i = lane + 1; i < n; i += kWave) dup |= key[i] == key[i - 1];
+  int n_inputs = 0;
+  for (int i = lane; i < n; i += kWave) n_inputs += key[i] < (long long)pop.n_in;
+  const bool dup_n = __ballot(dup) != 0;
+  n_inputs = wave_sum_int(n_inputs);
+  const int nn = n - n_inputs;
+  for (int k = lane; k < nn; k += kWave) {
+    const long long kk = key[n_inputs + k];
+    const int r = row[n_inputs + k];
+    const int64_t o = (int64_t)k * P + g;
+    ws.nodes.keyT[o] = kk;
+    ws.nodes.hT[o] = (int32_t)hash_mark(kk);
+    ws.nodes.a0T[o] = pop.node_bias[nb + r];
+    ws.nodes.a1T[o] = pop.node_resp[nb + r];
+    ws.nodes.codeT[o] = (uint32_t)pop.node_act[nb + r] | ((uint32_t)pop.node_agg[nb + r] << 8);
+  }
+  wave_sync();
+  // connection genes
+  n = 0;
+  for (int base = 0; base < (int)crows; base += kWave) {
+    const int r = base + lane;
+    int32_t a = -1, b = -1;
+    if (r < crows) {
+      a = pop.conn_in[cb + r];
+      b = pop.conn_out[cb + r];
+    }
+    const bool valid = a >= 0 && b >= 0;
+    const uint64_t m = __ballot(valid);
+    if (valid) {
+      key[n + mbcnt(m)] = ((long long)a << 32) | (long long)(uint32_t)b;
+      row[n + mbcnt(m)] = r;
+    }
+    n += __popcll(m);
+  }
+  for (int i = n + lane; i < S; i += kWave) {
+    key[i] = kPadKey;
+    row[i] = -1;
+  }
+  wave_sync();
+  wave_bitonic(key, row, S);
+  dup = false;
+  for (int i = lane + 1; i < n; i += kWave) dup |= key[i] == key[i - 1];
+  const bool dup_c = __ballot(dup) != 0;
+  for (int k = lane; k < n; k += kWave) {
+    const long long kk = key[k];
+    const int r = row[k];
+    const int64_t o = (int64_t)k * P + g;
+    ws.conns.keyT[o] = kk;
+    ws.conns.hT[o] = (int32_t)hash_mark(kk);
+    ws.conns.a0T[o] = pop.conn_w[cb + r];
+    ws.conns.a1T[o] = 0.0f;
+    ws.conns.codeT[o] = (uint32_t)(pop.conn_en[cb + r] != 0);
+  }
+  if (lane == 0) {
+    const bool bad = dup_n || dup_c;
+    ws.cnt_n[g] = bad ? -1 : nn;
+    ws.cnt_c[g] = bad ? -1 : n;
+  }
+}
+
+struct Gene {
+  float a0, a1;
+  uint32_t code;
+};
+
+__device__ __forceinline__ float attr_distance(Gene p, float a0, float a1, uint32_t code) {
+  float t = fabsf(p.a0 - a0) + fabsf(p.a1 - a1);
+  t += (p.code & 0xffu) != (code & 0xffu) ? 1.0f : 0.0f;
+  t += (p.code >> 8) != (code >> 8) ? 1.0f : 0.0f;
+  return t;
+}
+
+// Inserts row genome i's genes of one kind into an LDS hash of HC slots.
+__device__ __forceinline__ void fill_hash(const GeneList& l, int P, int i, int n, int HC,
+                                          long long* hk, Gene* hv) {
+  for (int k = threadIdx.x; k < n; k += kPairBlock) {
+    const int64_t o = (int64_t)k * P + i;
+    const long long key = l.keyT[o];
+    uint32_t h = (uint32_t)l.hT[o] & (uint32_t)(HC - 1);
+    while (atomicCAS((unsigned long long*)&hk[h], ~0ull, (unsigned long long)key) != ~0ull)
+      h = (h + 1) & (uint32_t)(HC - 1);
+    hv[h] = Gene{l.a0T[o], l.a1T[o], l.codeT[o]};
+  }
+}
+
+// Walks column genome j's sorted genes of one kind against the row hashes:
+// homologous counts and attribute sums per row, in ascending key order.
+__device__ __forceinline__ void walk_genes(const GeneList& l, int P, int j, int nj, int nr,
+                                           int i0, const int* ni, int HC,
+                                           const long long* hk_all, const Gene* hv_all,
+                                           int* hom, float* H) {
+  for (int k = 0; k < nj; ++k) {
+    const int64_t o = (int64_t)k * P + j;
+    const long long key = l.keyT[o];
+    const float a0 = l.a0T[o], a1 = l.a1T[o];
+    const uint32_t code = l.codeT[o];
+    const uint32_t h0 = (uint32_t)l.hT[o] & (uint32_t)(HC - 1);
+#pragma unroll
+    for (int r = 0; r < kMaxRows; ++r) {
+      if (r >= nr || ni[r] < 0 || j < i0 + r) continue;
+      const long long* hk = hk_all + (size_t)r * HC;
+      uint32_t h = h0;
+      while (true) {
+        const long long kk = hk[h];
+        if (kk == key) {
+          ++hom[r];
+          H[r] += attr_distance(hv_all[(size_t)r * HC + h], a0, a1, code);
+          break;
+        }
+        if (kk == -1) break;
+        h = (h + 1) & (uint32_t)(HC - 1);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float kind_term(int n1, int n2, int hom, float H, float c_d,
+                                           float c_h) {
+  const int n = max(n1, n2);
+  if (n == 0) return 0.0f;
+  return (c_d * (float)(n1 + n2 - 2 * hom) + c_h * H) / (float)n;
+}
+
+// Block = up to kMaxRows row genomes x 256 column genomes; LDS per row: the
+// node hash [HN] and the connection hash [HC] (keys, then attributes).
+__global__ __launch_bounds__(kPairBlock) void pair_nodes_kernel(WsN ws, int P, int HN, int HC,
+                                                                 int R, float c_d, float c_h,
+                                                                 float* dist, int32_t* DN_out,
+                                                                 int32_t* DC_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  long long* nk_all = (long long*)smem;                         // [R][HN]
+  long long* ck_all = nk_all + (size_t)R * HN;                  // [R][HC]
+  Gene* nv_all = (Gene*)(ck_all + (size_t)R * HC);              // [R][HN]
+  Gene* cv_all = nv_all + (size_t)R * HN;                       // [R][HC]
+  const int i0 = blockIdx.y * R;
+  const int j = blockIdx.x * kPairBlock + threadIdx.x;
+  const int nr = min(R, P - i0);
+  if ((int)(blockIdx.x * kPairBlock + kPairBlock - 1) < i0) return;  // all below the diagonal
+  for (int h = threadIdx.x; h < nr * HN; h += kPairBlock) nk_all[h] = -1;
+  for (int h = threadIdx.x; h < nr * HC; h += kPairBlock) ck_all[h] = -1;
+  __syncthreads();
+  for (int r = 0; r < nr; ++r) {
+    const int i = i0 + r;
+    const int nn = ws.cnt_n[i], nc = ws.cnt_c[i];
+    fill_hash(ws.nodes, P, i, nn, HN, nk_all + (size_t)r * HN, nv_all + (size_t)r * HN);
+    fill_hash(ws.conns, P, i, nc, HC, ck_all + (size_t)r * HC, cv_all + (size_t)r * HC);
+  }
+  __syncthreads();
+  if (j >= P) return;
+  const int nj_n = ws.cnt_n[j], nj_c = ws.cnt_c[j];
+  int ni_n[kMaxRows], ni_c[kMaxRows], hom_n[kMaxRows], hom_c[kMaxRows];
+  float H_n[kMaxRows], H_c[kMaxRows];
+#pragma unroll
+  for (int r = 0; r < kMaxRows; ++r) {
+    ni_n[r] = r < nr ? ws.cnt_n[i0 + r] : 0;
+    ni_c[r] = r < nr ? ws.cnt_c[i0 + r] : 0;
+    hom_n[r] = hom_c[r] = 0;
+    H_n[r] = H_c[r] = 0.0f;
+  }
+  walk_genes(ws.nodes, P, j, max(nj_n, 0), nr, i0, ni_n, HN, nk_all, nv_all, hom_n, H_n);
+  walk_genes(ws.conns, P, j, max(nj_c, 0), nr, i0, ni_c, HC, ck_all, cv_all, hom_c, H_c);
+#pragma unroll
+  for (int r = 0; r < kMaxRows; ++r) {
+    if (r >= nr || j < i0 + r) continue;
+    const int64_t o = (int64_t)(i0 + r) * P + j;
+    const int64_t ot = (int64_t)j * P + (i0 + r);
+    float d;
+    int dn, dc;
+    if (ni_n[r] < 0 || nj_n < 0) {
+      d = __builtin_nanf("");
+      dn = dc = -1;
+    } else {
+      d = kind_term(ni_n[r], nj_n, hom_n[r], H_n[r], c_d, c_h) +
+          kind_term(ni_c[r], nj_c, hom_c[r], H_c[r], c_d, c_h);
+      dn = ni_n[r] + nj_n - 2 * hom_n[r];
+      dc = ni_c[r] + nj_c - 2 * hom_c[r];
+    }
+    dist[o] = d;
+    dist[ot] = d;
+    if (DN_out) {
+      DN_out[o] = dn;
+      DC_out[o] = dc;
+      DN_out[ot] = dn;
+      DC_out[ot] = dc;
+    }
+  }
+}
+
 }  // namespace
 
 size_t distance_workspace_bytes(int P, int C_max) { return ws_bytes(P, C_max); }
@@ -329,6 +649,32 @@ int launch_distance(const tn_population& p, float c1, float c2, float c3, void* 
   dim3 grid((p.P + kPairBlock - 1) / kPairBlock, (p.P + R - 1) / R);
   hipLaunchKernelGGL(pair_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HC,
                      p.C_max, R, c1, c2, c3, dist, E, D);
+  return check_launch();
+}
+
+size_t distance_nodes_workspace_bytes(int P, int N_max, int C_max) {
+  return ws_nodes_bytes(P, N_max, C_max);
+}
+
+int launch_distance_nodes(const tn_population& p, float c_d, float c_h, void* workspace,
+                          float* dist, int32_t* DN, int32_t* DC, hipStream_t stream) {
+  const int S = next_pow2(std::max(p.N_max, p.C_max));
+  const size_t prep_lds = (sizeof(long long) + sizeof(int32_t)) * (size_t)S;
+  const int HN = next_pow2(2 * p.N_max), HC = next_pow2(2 * p.C_max);
+  const size_t per_row = (sizeof(long long) + sizeof(Gene)) * (size_t)(HN + HC);
+  const int R = (int)std::max<size_t>(1, std::min<size_t>(kMaxRows, (64 * 1024) / per_row));
+  const size_t pair_lds = per_row * R;
+  int rc = allow_lds((const void*)prep_nodes_kernel, prep_lds);
+  if (rc == TN_OK) rc = allow_lds((const void*)pair_nodes_kernel, pair_lds);
+  if (rc != TN_OK || p.P == 0) return rc;
+  WsN ws = carve_nodes(workspace, p.P, p.N_max, p.C_max);
+  hipLaunchKernelGGL(prep_nodes_kernel, dim3(p.P), dim3(kWave), prep_lds, stream, make_view(p),
+                     ws, S);
+  rc = check_launch();
+  if (rc != TN_OK) return rc;
+  dim3 grid((p.P + kPairBlock - 1) / kPairBlock, (p.P + R - 1) / R);
+  hipLaunchKernelGGL(pair_nodes_kernel, grid, dim3(kPairBlock), pair_lds, stream, ws, p.P, HN,
+                     HC, R, c_d, c_h, dist, DN, DC);
   return check_launch();
 }
 

@@ -12,5 +12,5 @@ from .population import (  # noqa: F401
     differentiation_population, cppn_population, permute_rows, insert_holes,
     to_ragged, to_padded, subset, xor_inputs, xor_targets, normal_obs,
     uniform_inputs, target_mlp, CONFIG_SEEDS, to_paper_layout,
-    reproduction_draws,
+    reproduction_draws, recurrent_population,
 )

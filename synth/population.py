@@ -42,7 +42,7 @@ AGG = {"sum": 0, "product": 1, "max": 2, "min": 3, "mean": 4, "maxabs": 5}
 
 # Seeds of the five workloads; observation seeds are these plus 100.
 CONFIG_SEEDS = {"xor": 1, "control": 2, "batching": 3, "differentiation": 4,
-                "cppn": 5}
+                "cppn": 5, "recurrent": 6}
 
 
 @dataclasses.dataclass
@@ -340,6 +340,37 @@ def cppn_population(seed: int = CONFIG_SEEDS["cppn"], P: int = 1000) -> Populati
     return grow_population(P, 5, 1, 32, 96, 30, rng,
                            hidden_acts=("sin", "gaussian", "tanh", "abs"),
                            output_acts=("tanh",))
+
+
+def recurrent_population(seed: int = CONFIG_SEEDS["recurrent"], P: int = 1000, back_edges: int = 12) -> Population:
+    """Recurrent-network sized: the control population's genomes (17 -> 6, N_max
+    64, C_max 256) plus up to ``back_edges`` extra enabled connections per
+    genome whose destination is a hidden node, an output or the source itself
+    (self-loops and edges against the growth order, so most genomes gain
+    cycles); weights N(0, 1) scaled by 0.5, markings kept unique."""
+    pop = control_population(P=P)
+    rng = np.random.default_rng(seed)
+    for g in range(P):
+        keys = pop.node_key[g][pop.node_key[g] >= 0]
+        srcs = keys[(keys < pop.n_in) | (keys >= pop.n_in + pop.n_out)]
+        srcs = np.concatenate([srcs, keys[(keys >= pop.n_in) & (keys < pop.n_in + pop.n_out)]])
+        dsts = keys[keys >= pop.n_in]
+        valid = (pop.conn_in[g] >= 0) & (pop.conn_out[g] >= 0)
+        present = set(zip(pop.conn_in[g][valid].tolist(), pop.conn_out[g][valid].tolist()))
+        free = list(np.flatnonzero(~valid))
+        for _ in range(back_edges):
+            if not free:
+                break
+            d = int(rng.choice(dsts))
+            a = d if rng.random() < 0.25 else int(rng.choice(srcs))
+            if (a, d) in present:
+                continue
+            r = free.pop(0)
+            pop.conn_in[g, r], pop.conn_out[g, r] = a, d
+            pop.conn_w[g, r] = np.float32(0.5 * rng.standard_normal())
+            pop.conn_en[g, r] = 1
+            present.add((a, d))
+    return pop
 
 
 # --------------------------------------------------------------------------

@@ -19,6 +19,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 _CACHE = {}
+RECURRENT_B = 1000      # observations per genome of the recurrent workload
+RECURRENT_T = 10        # sweeps of the recurrent workload
 
 
 def _workload(name):
@@ -36,6 +38,9 @@ def _workload(name):
         pop = synth.differentiation_population()
         X = synth.uniform_inputs(1024, 4, s["differentiation"] + 100)
         data = (X, synth.target_mlp(X, 32, 2, s["differentiation"] + 200))
+    elif name == "recurrent":
+        pop = synth.recurrent_population()
+        data = (synth.normal_obs(pop.P, RECURRENT_B, pop.n_in, s["recurrent"] + 100),)
     else:
         raise ValueError(name)
     _CACHE[name] = (pop, data)
@@ -55,6 +60,15 @@ def _forward_chunk(args):
         cs.append(c)
         st.append(tr.status)
     return lo, np.stack(ys), np.stack(cs), np.array(st)
+
+
+def _recurrent_chunk(args):
+    name, lo, hi = args
+    import oracle
+    pop, (obs,) = _workload(name)
+    Y, C, st = oracle.recurrent_population(pop, obs, RECURRENT_T, genomes=range(lo, hi),
+                                           with_cond=True)
+    return lo, Y, C, st
 
 
 def _grad_chunk(args):
@@ -94,6 +108,14 @@ def _run(fn, name, P, chunk):
 def forward_reference(name, P, chunk=250):
     """(Y [P][B][O], cond [P][B][O], status [P]) of the named workload."""
     parts = _run(_forward_chunk, name, P, chunk)
+    return (np.concatenate([p[1] for p in parts]), np.concatenate([p[2] for p in parts]),
+            np.concatenate([p[3] for p in parts]))
+
+
+def recurrent_reference(P, chunk=50):
+    """(Y [P][B][O], cond, status [P]) of the recurrent workload after
+    RECURRENT_T sweeps."""
+    parts = _run(_recurrent_chunk, "recurrent", P, chunk)
     return (np.concatenate([p[1] for p in parts]), np.concatenate([p[2] for p in parts]),
             np.concatenate([p[3] for p in parts]))
 

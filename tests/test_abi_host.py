@@ -160,3 +160,47 @@ def test_status_strings(lib):
         assert lib.tn_status_string(code).startswith(b"TN_")
     assert lib.tn_status_string(99) == b"unknown tn_status"
     assert lib.tn_version() >= 100
+
+
+def test_reproduce_and_node_distance_reject_bad_arguments_without_a_gpu(lib):
+    p = _fake_pop()
+    nu, nz = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.tn_reproduce_draws(16, 32, ctypes.byref(nu), ctypes.byref(nz)) == _abi.TN_OK
+    assert (nu.value, nz.value) == (16 + 7 * 16 + 2 * 32, 4 + 2 * 16 + 32)
+    assert lib.tn_reproduce_draws(0, 32, ctypes.byref(nu), ctypes.byref(nz)) == _abi.TN_EINVAL
+    n = ctypes.c_size_t()
+    assert lib.tn_reproduce_workspace_size(-1, ctypes.byref(n)) == _abi.TN_EINVAL
+    assert lib.tn_reproduce_workspace_size(100, ctypes.byref(n)) == _abi.TN_OK and n.value > 0
+    good = _abi.TnMutationParams(node_add=0.2, conn_add=0.4, n_act_options=1, n_agg_options=1)
+    arrays = _abi.TnPopulationArrays()
+    key_out = ctypes.cast(ctypes.c_void_p(0x6000), _abi.c_int32_p)
+    dummy_i = ctypes.cast(ctypes.c_void_p(0x7000), _abi.c_int32_p)
+    dummy_f = ctypes.cast(ctypes.c_void_p(0x8000), _abi.c_float_p)
+    ws = ctypes.c_void_p(0x9000)
+    # children arrays missing
+    assert lib.tn_reproduce(ctypes.byref(p), 4, dummy_i, dummy_f, dummy_f, ctypes.byref(good), 50,
+                            ctypes.byref(arrays), key_out, ws, None) == _abi.TN_EINVAL
+    bad = [dict(node_add=1.5), dict(conn_delete=float("nan")), dict(n_act_options=0),
+           dict(n_agg_options=9), dict(act_default=256)]
+    for kw in bad:
+        prm = _abi.TnMutationParams(node_add=0.2, conn_add=0.4, n_act_options=1, n_agg_options=1)
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        assert lib.tn_reproduce(ctypes.byref(p), 4, dummy_i, dummy_f, dummy_f, ctypes.byref(prm),
+                                50, ctypes.byref(arrays), key_out, ws, None) == _abi.TN_EINVAL, kw
+    unsorted = _abi.TnMutationParams(n_act_options=2, n_agg_options=1)
+    unsorted.act_options[0], unsorted.act_options[1] = 3, 1
+    assert lib.tn_reproduce(ctypes.byref(p), 4, dummy_i, dummy_f, dummy_f, ctypes.byref(unsorted),
+                            50, ctypes.byref(arrays), key_out, ws, None) == _abi.TN_EINVAL
+    ragged = _fake_pop(node_off=ctypes.cast(ctypes.c_void_p(0x2000), _abi.c_int64_p),
+                       conn_off=ctypes.cast(ctypes.c_void_p(0x3000), _abi.c_int64_p),
+                       total_nodes=77, total_conns=99)
+    assert lib.tn_reproduce(ctypes.byref(ragged), 4, dummy_i, dummy_f, dummy_f, ctypes.byref(good),
+                            50, ctypes.byref(arrays), key_out, ws, None) == _abi.TN_EUNSUPPORTED
+    assert lib.tn_distance_nodes_workspace_size(ctypes.byref(p), ctypes.byref(n)) == _abi.TN_OK
+    assert n.value > 0
+    E = ctypes.cast(ctypes.c_void_p(0x5000), _abi.c_int32_p)
+    assert lib.tn_distance_nodes(ctypes.byref(p), 1.0, 0.5, ws, dummy_f, E, None,
+                                 None) == _abi.TN_EINVAL
+    assert lib.tn_distance_nodes(ctypes.byref(p), 1.0, 0.5, None, dummy_f, None, None,
+                                 None) == _abi.TN_EINVAL
