@@ -24,6 +24,9 @@ It is the plain, slow definition of what the method computes, in float64
 * ``recurrent`` - forward pass of recurrent networks by synchronous sweeps
                  (network type of Appendix A; Section 3.3 covers only the
                  feedforward calculation).
+* ``neat``     - one NEAT generation (Algorithm 1's loop body: speciation,
+                 offspring counts, parent selection, reproduction) and the
+                 initial population.
 * ``reproduce`` - crossover and mutation as tensorized row operations
                  (Section 3.2; hyperparameters of Appendices A and C).
 
@@ -45,4 +48,5 @@ from .compat import (  # noqa: F401
 from .adjoint import backward, backward_population  # noqa: F401
 from . import hyperneat  # noqa: F401
 from . import reproduce  # noqa: F401
+from . import neat  # noqa: F401
 from .recurrent import recurrent_forward, recurrent_population, recurrent_status  # noqa: F401
