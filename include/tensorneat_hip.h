@@ -765,6 +765,105 @@ int tn_reproduce(const tn_population* pop, int32_t n_children, const int32_t* pa
                  int32_t next_key, const tn_population_arrays* children, int32_t* next_key_out,
                  void* workspace, hipStream_t stream);
 
+/* ------------------------------------------------------- NEAT generation */
+
+/*
+ * One generation of NEAT on a padded population (Algorithm 1's loop body:
+ * divide the population into species by the distances between networks,
+ * determine each species' number of new networks from the fitness, generate
+ * them by crossover and mutation), with the hyperparameters of Appendix A.
+ * The paper names these steps but not their rules; implemented here:
+ *
+ *  1. Speciation by the node-inclusive distance of tn_distance_nodes (c_d =
+ *     compatibility_disjoint, c_h = compatibility_homologous), evaluated in
+ *     float32 in ascending key order: every genome joins the alive species
+ *     whose representative is nearest if below compatibility_threshold (ties:
+ *     lowest slot); the others, in genome order, join the nearest species
+ *     founded earlier in this call if below the threshold, else found one in
+ *     the lowest free slot; with no free slot left, they join the nearest
+ *     alive species whatever the distance (NaN counts as infinite).
+ *  2. Species fitness = largest member fitness; it improves when above the
+ *     slot's best. Stagnant (no improvement for max_stagnation generations)
+ *     species get no children, except the species_elitism species of largest
+ *     fitness.
+ *  3. Children of each surviving species (float32, slot order): af = (mean
+ *     member fitness - lo) / max(hi - lo, 1) over surviving members' range;
+ *     target = P af / sum af; spawn = size + (target - size) *
+ *     spawn_number_change_rate (size = last generation's children, 0 for a new
+ *     species); share = spawn P / sum spawn; counts = floor(share), the rest
+ *     one each by largest remainder (ties: lowest slot); the counts sum to P.
+ *  4. Parents, children laid out by slot then rank: members ranked by fitness
+ *     (largest first, ties lower index); the first min(genome_elitism, count,
+ *     members) children copy ranks 0.. unchanged; each other child c takes
+ *     ranks floor(sel[c][k] * m) (k = 0, 1) among the m = max(1,
+ *     ceil(survival_threshold * members)) best, the fitter first.
+ *  5. Children by tn_reproduce with U, Z, next_key (next_key_out as there).
+ *  6. The table: surviving species with children keep their slot, rank-0
+ *     member as representative, their count as size; the other slots are freed.
+ *
+ *   pop          padded population (ragged: TN_EUNSUPPORTED), P >= 1
+ *   fitness      device float32 [P], finite (non-finite values give
+ *                unspecified but in-range species and counts)
+ *   generation   the generation index (stagnation clock)
+ *   table        device species table (tn_species_table), read and updated
+ *   sel          device float32 [P][2] selection uniforms in [0, 1)
+ *   U, Z         reproduction draws as tn_reproduce
+ *   children     device [P][N_max] / [P][C_max] arrays (not overlapping pop)
+ *   species_of   device int32 [P] or NULL: the slot each genome joined
+ *   parents      device int32 [P][2] or NULL: the parent pairs used
+ *   workspace    tn_neat_workspace_size bytes
+ * TN_EINVAL for bad parameters (max_species outside 1..TN_NEAT_MAX_SPECIES,
+ * species_elitism < 1, max_stagnation < 1, genome_elitism < 0,
+ * survival_threshold outside (0, 1], spawn rate outside [0, 1], a negative or
+ * non-finite threshold or coefficient, mutation parameters as tn_reproduce).
+ */
+#define TN_NEAT_MAX_SPECIES 64
+
+typedef struct tn_neat_params {
+    float   compatibility_threshold;
+    float   compatibility_disjoint;
+    float   compatibility_homologous;
+    int32_t max_species;
+    int32_t species_elitism;
+    int32_t max_stagnation;
+    int32_t genome_elitism;
+    float   survival_threshold;
+    float   spawn_number_change_rate;
+    tn_mutation_params mutation;
+} tn_neat_params;
+
+/* Species table, device arrays owned by the caller: max_species slots. */
+typedef struct tn_species_table {
+    int32_t max_species;
+    tn_population_arrays reps;   /* representatives, [max_species][N_max] / [max_species][C_max] */
+    int32_t* alive;              /* [max_species] 1 for a slot in use                       */
+    float*   best;               /* [max_species] best species fitness so far               */
+    int32_t* last_improved;      /* [max_species] generation of the last improvement        */
+    int32_t* size;               /* [max_species] children given in the last generation     */
+} tn_species_table;
+
+/* The initial population (Algorithm 1's first step): genome g holds the
+ * input and output nodes (keys 0 .. n_in + n_out - 1) in its first node rows and
+ * every input -> output connection, enabled, in row i * n_out + o; node bias
+ * and response and connection weights are init_mean + init_std * z with the
+ * normals Z [P][n_normal] in tn_reproduce's layout (Z[4 + 2r + k] for node row
+ * r, Z[4 + 2 N_max + r] for connection row r); act / agg the defaults. The
+ * other rows are empty. table (may be NULL) is cleared: no slot alive.
+ * Needs n_in + n_out <= N_max and n_in * n_out <= C_max. */
+int tn_neat_init(int32_t P, int32_t n_in, int32_t n_out, int32_t N_max, int32_t C_max,
+                 const float* Z, const tn_mutation_params* mutation,
+                 const tn_population_arrays* out, const tn_species_table* table,
+                 hipStream_t stream);
+
+int tn_neat_workspace_size(const tn_population* pop, int32_t max_species, size_t* bytes);
+
+int tn_neat_generation(const tn_population* pop, const float* fitness, int32_t generation,
+                       const tn_neat_params* params, const tn_species_table* table,
+                       const float* sel, const float* U, const float* Z, int32_t next_key,
+                       const tn_population_arrays* children, int32_t* species_of,
+                       int32_t* parents, int32_t* next_key_out, void* workspace,
+                       hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,5 +14,6 @@ from .api import (  # noqa: F401
     backward, forward_backward_mse, Plan, cppn_query, substrate_forward,
     substrate_backward, cppn_backward, pack_paper_layout, distance_noalloc, distance_nodes,
     MutationParams, reproduce, reproduce_draws, forward_recurrent,
+    NeatParams, SpeciesTable, neat_init, neat_generation,
 )
 from .autograd import TNForward  # noqa: F401

@@ -84,6 +84,20 @@ class TnMutationParams(ctypes.Structure):
          ("allow_cycles", ctypes.c_int32)])
 
 
+class TnNeatParams(ctypes.Structure):
+    _fields_ = [("compatibility_threshold", ctypes.c_float), ("compatibility_disjoint", ctypes.c_float),
+                ("compatibility_homologous", ctypes.c_float), ("max_species", ctypes.c_int32),
+                ("species_elitism", ctypes.c_int32), ("max_stagnation", ctypes.c_int32),
+                ("genome_elitism", ctypes.c_int32), ("survival_threshold", ctypes.c_float),
+                ("spawn_number_change_rate", ctypes.c_float), ("mutation", TnMutationParams)]
+
+
+class TnSpeciesTable(ctypes.Structure):
+    _fields_ = [("max_species", ctypes.c_int32), ("reps", TnPopulationArrays),
+                ("alive", c_int32_p), ("best", c_float_p), ("last_improved", c_int32_p),
+                ("size", c_int32_p)]
+
+
 class TnBucketInfo(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("rows_class", ctypes.c_int32),
                 ("count", ctypes.c_int32), ("edges", ctypes.c_int64), ("tile", TnTile)]
@@ -134,6 +148,18 @@ SIGNATURES = {
                                     ctypes.c_void_p, _STREAM]),
     "tn_forward_recurrent": (ctypes.c_int, [_POP, c_float_p, ctypes.c_int64, ctypes.c_int32,
                                             ctypes.c_int32, c_float_p, c_int32_p, _STREAM]),
+    "tn_neat_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, c_float_p, ctypes.POINTER(TnMutationParams),
+                                    ctypes.POINTER(TnPopulationArrays),
+                                    ctypes.POINTER(TnSpeciesTable), _STREAM]),
+    "tn_neat_workspace_size": (ctypes.c_int, [_POP, ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "tn_neat_generation": (ctypes.c_int, [_POP, c_float_p, ctypes.c_int32,
+                                          ctypes.POINTER(TnNeatParams),
+                                          ctypes.POINTER(TnSpeciesTable), c_float_p, c_float_p,
+                                          c_float_p, ctypes.c_int32,
+                                          ctypes.POINTER(TnPopulationArrays), c_int32_p,
+                                          c_int32_p, c_int32_p, ctypes.c_void_p, _STREAM]),
     "tn_plan_create": (ctypes.c_int, [_POP, _TR, ctypes.c_int32, ctypes.c_char_p,
                                       ctypes.POINTER(ctypes.c_void_p), _STREAM]),
     "tn_plan_destroy": (None, [ctypes.c_void_p]),

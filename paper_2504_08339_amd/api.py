@@ -426,6 +426,18 @@ class MutationParams:
         return c
 
 
+def _padded_arrays(n: int, N_max: int, C_max: int, device):
+    """Fresh [n][N_max] / [n][C_max] tensors and their tn_population_arrays."""
+    ts = {k: torch.empty((n, N_max), dtype=dt, device=device) for k, dt in _NODE.items()}
+    ts.update({k: torch.empty((n, C_max), dtype=dt, device=device) for k, dt in _CONN.items()})
+    arrays = _abi.TnPopulationArrays(*[_p(ts[k], ty) for k, ty in (
+        ("node_key", _abi.c_int32_p), ("node_bias", _abi.c_float_p),
+        ("node_resp", _abi.c_float_p), ("node_act", _abi.c_uint8_p),
+        ("node_agg", _abi.c_uint8_p), ("conn_in", _abi.c_int32_p), ("conn_out", _abi.c_int32_p),
+        ("conn_w", _abi.c_float_p), ("conn_en", _abi.c_uint8_p))])
+    return ts, arrays
+
+
 def reproduce_draws(N_max: int, C_max: int):
     """(uniforms, normals) tn_reproduce reads per child."""
     nu, nz = ctypes.c_int32(), ctypes.c_int32()
@@ -452,13 +464,7 @@ def reproduce(pop: Population, parents: torch.Tensor, U: torch.Tensor, Z: torch.
     _need(U, "U", torch.float32, (n, nu), d)
     _need(Z, "Z", torch.float32, (n, nz), d)
     prm = (params or MutationParams()).to_c()
-    ts = {k: torch.empty((n, pop.N_max), dtype=dt, device=d) for k, dt in _NODE.items()}
-    ts.update({k: torch.empty((n, pop.C_max), dtype=dt, device=d) for k, dt in _CONN.items()})
-    arrays = _abi.TnPopulationArrays(*[_p(ts[k], ty) for k, ty in (
-        ("node_key", _abi.c_int32_p), ("node_bias", _abi.c_float_p),
-        ("node_resp", _abi.c_float_p), ("node_act", _abi.c_uint8_p),
-        ("node_agg", _abi.c_uint8_p), ("conn_in", _abi.c_int32_p), ("conn_out", _abi.c_int32_p),
-        ("conn_w", _abi.c_float_p), ("conn_en", _abi.c_uint8_p))])
+    ts, arrays = _padded_arrays(n, pop.N_max, pop.C_max, d)
     nb = ctypes.c_size_t()
     _check("tn_reproduce_workspace_size", _lib.tn_reproduce_workspace_size(n, ctypes.byref(nb)))
     ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=d)
@@ -468,6 +474,102 @@ def reproduce(pop: Population, parents: torch.Tensor, U: torch.Tensor, Z: torch.
         _p(Z, _abi.c_float_p), ctypes.byref(prm), int(next_key), ctypes.byref(arrays),
         _p(nk, _abi.c_int32_p), ctypes.c_void_p(ws.data_ptr()), _stream(d)))
     return Population(pop.n_in, pop.n_out, pop.N_max, pop.C_max, ts), nk
+
+
+@dataclasses.dataclass
+class NeatParams:
+    """Generation hyperparameters (Appendix A; values of Appendix C)."""
+    compatibility_threshold: float = 3.5
+    compatibility_disjoint: float = 1.0
+    compatibility_homologous: float = 0.5
+    max_species: int = 10
+    species_elitism: int = 2
+    max_stagnation: int = 15
+    genome_elitism: int = 2
+    survival_threshold: float = 0.2
+    spawn_number_change_rate: float = 0.5
+    mutation: MutationParams = dataclasses.field(default_factory=MutationParams)
+
+    def to_c(self) -> "_abi.TnNeatParams":
+        c = _abi.TnNeatParams()
+        for f in dataclasses.fields(self):
+            if f.name == "mutation":
+                c.mutation = self.mutation.to_c()
+            else:
+                setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+class SpeciesTable:
+    """Device species table (tn_species_table): representatives [S][N_max] /
+    [S][C_max] and per-slot alive, best, last_improved, size."""
+
+    def __init__(self, max_species: int, N_max: int, C_max: int, device):
+        self.max_species = int(max_species)
+        self.reps, arrays = _padded_arrays(self.max_species, N_max, C_max, device)
+        i32 = dict(dtype=torch.int32, device=device)
+        self.alive = torch.zeros(self.max_species, **i32)
+        self.best = torch.full((self.max_species,), float("-inf"), dtype=torch.float32,
+                               device=device)
+        self.last_improved = torch.zeros(self.max_species, **i32)
+        self.size = torch.zeros(self.max_species, **i32)
+        self.c = _abi.TnSpeciesTable(self.max_species, arrays, _p(self.alive, _abi.c_int32_p),
+                                     _p(self.best, _abi.c_float_p),
+                                     _p(self.last_improved, _abi.c_int32_p),
+                                     _p(self.size, _abi.c_int32_p))
+
+
+def neat_init(P: int, n_in: int, n_out: int, N_max: int, C_max: int, Z: torch.Tensor,
+              mutation: Optional[MutationParams] = None, max_species: Optional[int] = None):
+    """(initial population, cleared species table) of tn_neat_init; Z [P][n_normal]."""
+    d = Z.device
+    _, nz = reproduce_draws(N_max, C_max)
+    _need(Z, "Z", torch.float32, (P, nz), d)
+    m = mutation or MutationParams()
+    ts, arrays = _padded_arrays(P, N_max, C_max, d)
+    table = SpeciesTable(max_species or NeatParams().max_species, N_max, C_max, d)
+    _check("tn_neat_init", _lib.tn_neat_init(P, n_in, n_out, N_max, C_max, _p(Z, _abi.c_float_p),
+                                             ctypes.byref(m.to_c()), ctypes.byref(arrays),
+                                             ctypes.byref(table.c), _stream(d)))
+    return Population(n_in, n_out, N_max, C_max, ts), table
+
+
+def neat_generation(pop: Population, fitness: torch.Tensor, generation: int,
+                    table: SpeciesTable, sel: torch.Tensor, U: torch.Tensor, Z: torch.Tensor,
+                    next_key, params: Optional[NeatParams] = None):
+    """One generation (tn_neat_generation): returns (children, species_of [P],
+    parents [P][2], next unused key as a device int32 tensor [1]). ``next_key``
+    is an int. The table is updated in place."""
+    prm = params or NeatParams()
+    if table.max_species != prm.max_species:
+        raise ValueError("table and params disagree on max_species")
+    if pop.ragged:
+        raise ValueError("neat_generation takes a padded population")
+    d, P = pop.device, pop.P
+    nu, nz = reproduce_draws(pop.N_max, pop.C_max)
+    _need(fitness, "fitness", torch.float32, (P,), d)
+    _need(sel, "sel", torch.float32, (P, 2), d)
+    _need(U, "U", torch.float32, (P, nu), d)
+    _need(Z, "Z", torch.float32, (P, nz), d)
+    if table.reps["node_key"].shape != (table.max_species, pop.N_max) or \
+            table.reps["conn_in"].shape != (table.max_species, pop.C_max) or \
+            table.alive.device != torch.device(d):
+        raise ValueError("species table shaped for another population or device")
+    ts, arrays = _padded_arrays(P, pop.N_max, pop.C_max, d)
+    nb = ctypes.c_size_t()
+    _check("tn_neat_workspace_size", _lib.tn_neat_workspace_size(
+        ctypes.byref(pop.c), prm.max_species, ctypes.byref(nb)))
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=d)
+    sp = torch.empty(P, dtype=torch.int32, device=d)
+    par = torch.empty((P, 2), dtype=torch.int32, device=d)
+    nk = torch.empty(1, dtype=torch.int32, device=d)
+    _check("tn_neat_generation", _lib.tn_neat_generation(
+        ctypes.byref(pop.c), _p(fitness, _abi.c_float_p), int(generation),
+        ctypes.byref(prm.to_c()), ctypes.byref(table.c), _p(sel, _abi.c_float_p),
+        _p(U, _abi.c_float_p), _p(Z, _abi.c_float_p), int(next_key), ctypes.byref(arrays),
+        _p(sp, _abi.c_int32_p), _p(par, _abi.c_int32_p), _p(nk, _abi.c_int32_p),
+        ctypes.c_void_p(ws.data_ptr()), _stream(d)))
+    return Population(pop.n_in, pop.n_out, pop.N_max, pop.C_max, ts), sp, par, nk
 
 
 class Plan:

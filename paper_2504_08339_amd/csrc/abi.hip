@@ -39,6 +39,16 @@ size_t distance_workspace_bytes(int P, int C_max);
 int launch_distance(const tn_population& p, float c1, float c2, float c3, void* workspace,
                     float* dist, int32_t* E, int32_t* D, hipStream_t stream);
 int noalloc_scratch(void** out);
+size_t neat_workspace_bytes(int P, int S, int N, int C);
+int launch_neat_init(int P, int n_in, int n_out, int N, int C, const float* Z,
+                     const tn_mutation_params& m, const tn_population_arrays& out,
+                     const tn_species_table* table, hipStream_t stream);
+int launch_neat_generation(const tn_population& p, const float* fit, int gen,
+                           const tn_neat_params& prm, const tn_species_table& table,
+                           const float* sel, const float* U, const float* Z, int32_t next_key,
+                           const tn_population_arrays& children, int32_t* species_of,
+                           int32_t* parents, int32_t* next_key_out, void* workspace,
+                           hipStream_t stream);
 int recurrent_lds_check(const tn_population& p, size_t* bytes);
 int launch_forward_recurrent(const tn_population& p, const float* obs, int64_t obs_stride, int B,
                              int T, float* out, int32_t* status, hipStream_t stream);
@@ -464,6 +474,75 @@ int tn_forward_recurrent(const tn_population* pop, const float* obs, int64_t obs
   rc = recurrent_lds_check(*pop, &bytes);
   if (rc != TN_OK) return rc;
   return launch_forward_recurrent(*pop, obs, obs_genome_stride, B, T, out, status, stream);
+}
+
+namespace {
+bool arrays_ok(const tn_population_arrays* o) {
+  return o && o->node_key && o->node_bias && o->node_resp && o->node_act && o->node_agg &&
+         o->conn_in && o->conn_out && o->conn_w && o->conn_en;
+}
+
+bool finite_nonneg(float x) { return x >= 0.0f && x < 3.0e38f; }  // false for NaN / inf
+
+int check_table(const tn_species_table* t) {
+  if (!t || t->max_species < 1 || t->max_species > TN_NEAT_MAX_SPECIES) return TN_EINVAL;
+  if (!arrays_ok(&t->reps) || !t->alive || !t->best || !t->last_improved || !t->size)
+    return TN_EINVAL;
+  return TN_OK;
+}
+}  // namespace
+
+int tn_neat_init(int32_t P, int32_t n_in, int32_t n_out, int32_t N_max, int32_t C_max,
+                 const float* Z, const tn_mutation_params* mutation,
+                 const tn_population_arrays* out, const tn_species_table* table,
+                 hipStream_t stream) {
+  if (P < 0 || n_in < 0 || n_out < 1 || N_max < 1 || C_max < 1) return TN_EINVAL;
+  if (N_max > TN_MAX_NODES || C_max > TN_MAX_CONNS) return TN_EUNSUPPORTED;
+  if (n_in + n_out > N_max || (int64_t)n_in * n_out > C_max) return TN_ESHAPE;
+  int rc = check_params(mutation);
+  if (rc != TN_OK) return rc;
+  if (P > 0 && (!Z || !arrays_ok(out))) return TN_EINVAL;
+  if (table) {
+    rc = check_table(table);
+    if (rc != TN_OK) return rc;
+  }
+  return launch_neat_init(P, n_in, n_out, N_max, C_max, Z, *mutation, *out, table, stream);
+}
+
+int tn_neat_workspace_size(const tn_population* pop, int32_t max_species, size_t* bytes) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (!bytes || max_species < 1 || max_species > TN_NEAT_MAX_SPECIES) return TN_EINVAL;
+  *bytes = neat_workspace_bytes(pop->P, max_species, pop->N_max, pop->C_max);
+  return TN_OK;
+}
+
+int tn_neat_generation(const tn_population* pop, const float* fitness, int32_t generation,
+                       const tn_neat_params* params, const tn_species_table* table,
+                       const float* sel, const float* U, const float* Z, int32_t next_key,
+                       const tn_population_arrays* children, int32_t* species_of,
+                       int32_t* parents, int32_t* next_key_out, void* workspace,
+                       hipStream_t stream) {
+  int rc = check_population(pop);
+  if (rc != TN_OK) return rc;
+  if (pop->node_off) return TN_EUNSUPPORTED;
+  if (pop->P < 1 || !params) return TN_EINVAL;
+  const tn_neat_params& m = *params;
+  if (!finite_nonneg(m.compatibility_threshold) || !finite_nonneg(m.compatibility_disjoint) ||
+      !finite_nonneg(m.compatibility_homologous) || m.max_species < 1 ||
+      m.max_species > TN_NEAT_MAX_SPECIES || m.species_elitism < 1 || m.max_stagnation < 1 ||
+      m.genome_elitism < 0 || !(m.survival_threshold > 0.0f && m.survival_threshold <= 1.0f) ||
+      !(m.spawn_number_change_rate >= 0.0f && m.spawn_number_change_rate <= 1.0f))
+    return TN_EINVAL;
+  rc = check_params(&m.mutation);
+  if (rc != TN_OK) return rc;
+  rc = check_table(table);
+  if (rc != TN_OK) return rc;
+  if (table->max_species != m.max_species) return TN_ESHAPE;
+  if (!fitness || !sel || !U || !Z || !arrays_ok(children) || !next_key_out || !workspace)
+    return TN_EINVAL;
+  return launch_neat_generation(*pop, fitness, generation, m, *table, sel, U, Z, next_key,
+                                *children, species_of, parents, next_key_out, workspace, stream);
 }
 
 int tn_cppn_query(const tn_population* pop, const tn_transformed* tr, const tn_substrate* sub,
