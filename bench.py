@@ -19,15 +19,30 @@ Beside it (`workloads`), each with its own timed steps and roofline:
                    with the fused MSE loss;
   hyperneat        1000 CPPNs on a 32x32 / 32x32 / 8 grid substrate, 128 obs per
                    genome: CPPN query + substrate forward + substrate backward +
-                   CPPN adjoint.
+                   CPPN adjoint;
+  xor              150 XOR genomes (16 / 32 rows), the four XOR rows: transform +
+                   forward with the fused fitness (microseconds per call);
+  recurrent        1000 recurrent genomes 17 -> 6 (control population plus back
+                   edges), 1000 obs each, 10 synchronous sweeps;
+  reproduce        1000 children of the control population (crossover +
+                   mutation, Appendix C rates, draws resident on the device);
+  distance_nodes   1000 x 1000 node-inclusive compatibility distance;
+  neat_xor         one NEAT generation on XOR, 150 genomes: transform + fitness +
+                   speciation + offspring counts + parents + reproduction (the
+                   draws made on the device by torch inside the step).
 
 `value` is genome-forward passes per second (P * B per step / time per step).
 The roofline object is for the dominant kernel of the headline step: every
 bucket's persistent kernel is also launched alone, bracketed by HIP events on
 the stream it runs on, and the slowest one's algorithmic bytes (observations
 read, outputs written and the program words its genomes read, counted from
-the actual population) over its average duration give `achieved`. The CPU
-oracle is timed on a bounded sample for `cpu_baseline`.
+the actual population) over its average duration give `achieved`. Beside the HBM
+roofline, a vector-ALU one: lane-operations per forward pass counted from the
+actual programs (one fused multiply-add per enabled in-edge, one for z and the
+activation's instructions per non-input node) over the non-packed float32 peak
+of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-operations/s; the
+larger of the two fractions names the binding roof. The CPU oracle is timed on
+a bounded sample, fanned out over the host cores, for `cpu_baseline`.
 """
 from __future__ import annotations
 
@@ -44,6 +59,26 @@ METRIC = ("genome-forward-passes/s (pop×obs) + % HBM roofline; "
           "batched-persistent vs plain launch")
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # non-packed float32 lane-ops/s
+# vector instructions of each activation in the forward engines (act code order:
+# identity, sigmoid, tanh, relu, sin, gaussian, abs); tanh evaluates both its
+# branches and selects, sin includes the range reduction of sinf
+ACT_LANE_OPS = (0, 4, 16, 1, 24, 3, 1)
+
+
+def lane_ops_per_pass(pop, ne):
+    """VALU lane-operations of one forward pass per genome: one FMA per
+    enabled in-edge (ne), and per non-input node one FMA for z plus its
+    activation's instructions."""
+    import numpy as np
+    cost = np.array(ACT_LANE_OPS, np.int64)
+    out = np.zeros(pop.P, np.int64)
+    for g in range(pop.P):
+        rows = pop.node_rows(g)
+        key, act = rows["key"], rows["act"]
+        m = key >= pop.n_in
+        out[g] = int(np.sum(1 + cost[np.minimum(act[m], 6)]))
+    return out + ne
 
 
 def _args():
@@ -59,6 +94,18 @@ def _args():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
+
+
+def _roof(bytes_, lane_ops, ms, extra=None):
+    """HBM and VALU fractions of one timed kernel; `bound` is the larger."""
+    gbs = bytes_ / (ms * 1e-3) / 1e9
+    lops = lane_ops / (ms * 1e-3)
+    hbm, alu = gbs / HBM_PEAK_GBS, lops / VALU_PEAK_LANE_OPS
+    r = {"hbm_achieved_GBs": gbs, "hbm_frac": hbm, "alu_achieved_lane_ops_per_s": lops,
+         "alu_frac": alu, "binding": "alu" if alu > hbm else "hbm",
+         "algorithmic_bytes": int(bytes_), "lane_ops": int(lane_ops), "avg_ms": ms}
+    r.update(extra or {})
+    return r
 
 
 def _log(msg):
@@ -168,18 +215,35 @@ def batching(torch, tn, synth, args):
     _, bms = timed_steps(torch, per_bucket, args.steps, args.warmup)
     bucket_ms = [bms[f"bucket{i}"] for i in range(len(buckets))]
     dom = int(np.argmax(bucket_ms))
+    lops = lane_ops_per_pass(pop, ne) * B
+    bucket_lops = [int(lops[m].sum()) for m in lists]
     achieved = bucket_bytes[dom] / (bucket_ms[dom] * 1e-3) / 1e9
+    alu = bucket_lops[dom] / (bucket_ms[dom] * 1e-3)
     eng = {1: "lds", 2: "register"}
     kern = ("forward_rf_queue_kernel" if buckets[dom]["engine"] == 2
             else "forward_queue_kernel")
     traffic = recorded_traffic(eng[buckets[dom]["engine"]], buckets[dom]["obs_per_lane"],
                                buckets[dom]["rows_class"])
-    roofline = {"bound": "hbm", "kernel": f"{kern} (bucket {dom}: "
-                f"{eng[buckets[dom]['engine']]} engine, {buckets[dom]['obs_per_lane']} obs per "
-                f"lane, rows <= {buckets[dom]['rows_class']})",
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes": bucket_bytes[dom], "avg_ms": bucket_ms[dom]}
+    name = (f"{kern} (bucket {dom}: {eng[buckets[dom]['engine']]} engine, "
+            f"{buckets[dom]['obs_per_lane']} obs per lane, rows <= {buckets[dom]['rows_class']})")
+    if alu / VALU_PEAK_LANE_OPS > achieved / HBM_PEAK_GBS:
+        roofline = {"bound": "alu", "kernel": name, "achieved": alu / 1e12,
+                    "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                    "frac": alu / VALU_PEAK_LANE_OPS, "traffic": traffic,
+                    "lane_ops": bucket_lops[dom], "hbm_GBs": achieved,
+                    "hbm_frac": achieved / HBM_PEAK_GBS,
+                    "algorithmic_bytes": bucket_bytes[dom], "avg_ms": bucket_ms[dom]}
+    else:
+        roofline = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "alu_frac": alu / VALU_PEAK_LANE_OPS, "lane_ops": bucket_lops[dom],
+                    "algorithmic_bytes": bucket_bytes[dom], "avg_ms": bucket_ms[dom]}
+    _log("batching: transform + forward steps")
+
+    def with_transform(t):
+        t("transform", tn.transform, dp, out=tr)
+        t("graph", plan.forward, obs, out)
+    tf_ms, tf_calls = timed_steps(torch, with_transform, args.steps, args.warmup)
     passes = pop.P * B
     info = {
         "workload": "batching: 10000 genomes, hidden nodes log-uniform 10..500, "
@@ -195,8 +259,14 @@ def batching(torch, tn, synth, args):
         "algorithmic_bytes_per_step": total_bytes,
         "plain_per_bucket": {"value": passes / (plain_ms * 1e-3), "ms_per_step": plain_ms,
                              "persistent_graph_speedup": plain_ms / graph_ms},
-        "buckets": [{**b, "ms_alone": m, "algorithmic_bytes": by}
-                    for b, m, by in zip(buckets, bucket_ms, bucket_bytes)],
+        "whole_step_alu_frac": int(lops.sum()) / (graph_ms * 1e-3) / VALU_PEAK_LANE_OPS,
+        "lane_ops_per_step": int(lops.sum()),
+        "transform_plus_forward": {"value": passes / (tf_ms * 1e-3), "ms_per_step": tf_ms,
+                                   "transform_ms": tf_calls["transform"]},
+        "buckets": [{**b, "ms_alone": m, "algorithmic_bytes": by, "lane_ops": lo,
+                     "hbm_frac": by / (m * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "alu_frac": lo / (m * 1e-3) / VALU_PEAK_LANE_OPS}
+                    for b, m, by, lo in zip(buckets, bucket_ms, bucket_bytes, bucket_lops)],
     }
     return res, pop, obs_np
 
@@ -249,27 +319,60 @@ def bucket_members(pop, tr, buckets):
     return lists
 
 
-def cpu_baseline_forward(pop, obs, budget_s, label):
-    """The oracle as it stands, one process: transform + forward of a sample of
-    genomes with all their observations, scaled to passes per second."""
-    import numpy as np
+def _oracle_worker(args):
+    """One single-threaded worker: decode + transform + forward of its genomes
+    (a ragged subset with their observations) until the time budget runs out;
+    returns (genomes done, seconds)."""
+    sub, obs, budget_s = args
     import oracle
-    rng = np.random.default_rng(0)
-    order = rng.permutation(pop.P)
     t0 = time.perf_counter()
-    n_g = 0
-    while time.perf_counter() - t0 < budget_s and n_g < pop.P:
-        g = int(order[n_g])
-        gen = oracle.decode(pop, g)
+    done = 0
+    for g in range(sub.P):
+        if time.perf_counter() - t0 >= budget_s:
+            break
+        gen = oracle.decode(sub, g)
         oracle.forward(gen, oracle.transform(gen), obs[g])
-        n_g += 1
-    sec = time.perf_counter() - t0
+        done += 1
+    return done, time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_forward(pop, obs, budget_s, label):
+    """The oracle as it stands, fanned out over the host cores this process may
+    use (at most 16, the share of one GPU on the box): every worker process
+    takes an interleaved slice of a random genome order with all its
+    observations and runs until the budget; passes per second = all passes
+    done / the slowest worker's time."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import numpy as np
+    import synth
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    order = np.random.default_rng(0).permutation(pop.P)
+    jobs = []
+    for w in range(cores):
+        idx = [int(g) for g in order[w::cores]]
+        jobs.append((synth.subset(pop, idx), obs[idx], budget_s))
+    with cf.ProcessPoolExecutor(cores, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_oracle_worker, jobs))
+    n_g = sum(r[0] for r in res)
+    sec = max(r[1] for r in res)
     B = obs.shape[1]
-    return {"value": n_g * B / sec, "unit": "genome-forward-passes/s", "cores": 1,
-            "kind": "oracle",
+    return {"value": n_g * B / sec, "unit": "genome-forward-passes/s", "cores": cores,
+            "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"{n_g} random genomes of the {label} population x all {B} observations "
-                      f"each (decode + transform + forward), float64 NumPy, one process, "
-                      f"{sec:.1f} s"}
+                      f"each (decode + transform + forward), float64 NumPy, {cores} "
+                      f"single-threaded worker processes, {sec:.1f} s"}
 
 
 # ------------------------------------------------------------------- control
@@ -299,6 +402,12 @@ def control(torch, tn, synth, args):
     fwd_bytes = (4 * pop.P * B * (I + O) + int(np.sum(4 * (nv + 1) + 20 * nv + 8 * ne))
                  + 4 * pop.P * (I + O) + 8 * pop.P)
     achieved = fwd_bytes / (ms["forward"] * 1e-3) / 1e9
+    lops = int(lane_ops_per_pass(pop, ne).sum()) * B
+    # distance: each pair walks the column genome's genes once, probing the
+    # row genome's hash (about 10 lane-ops per probe: hash load, key compare,
+    # branch, count, |dw| and sum), plus the row genome's binary search
+    genes = np.array([int(np.sum(pop.conn_rows(g)["in"] >= 0)) for g in range(pop.P)])
+    dist_lops = 10 * int(np.sum(genes)) * pop.P // 2 + 10 * pop.P * pop.P // 2
     return {
         "workload": "control-policy: 1000 genomes, 17 -> 6, N_max 64, C_max 256, 1000 N(0,1) "
                     "observations per genome; step = transform + forward (the library's "
@@ -306,10 +415,10 @@ def control(torch, tn, synth, args):
                     "wavefront) + 1000 x 1000 compatibility distance",
         "value": pop.P * B / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
         "ms_per_step": step_ms, "call_ms": ms,
-        "forward_roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                             "algorithmic_bytes": fwd_bytes},
+        "forward_roofline": _roof(fwd_bytes, lops, ms["forward"]),
         "distance_pairs_per_s": pop.P * pop.P / (ms["distance"] * 1e-3),
+        "distance_roofline": _roof(4 * pop.P * pop.P * 3 + 13 * int(genes.sum()), dist_lops,
+                                   ms["distance"]),
     }
 
 
@@ -330,16 +439,16 @@ def differentiation(torch, tn, synth, args):
     # gradients written + program read twice (forward and reverse sweep) + data
     by = int(4 * pop.P * (pop.C_max + pop.N_max) + 2 * np.sum(24 * nv + 8 * ne)
              + X.nbytes + T.nbytes)
-    achieved = by / (ms["forward_backward_mse"] * 1e-3) / 1e9
+    # forward lane-ops, then per node act' (about 4) + delta + bias sum, and per
+    # edge the dW and upstream-gradient FMAs
+    nodes = np.array([int(np.sum(pop.node_rows(g)["key"] >= pop.n_in)) for g in range(pop.P)])
+    lops = int((lane_ops_per_pass(pop, ne) + 6 * nodes + 2 * ne).sum()) * 1024
     return {
         "workload": "differentiation: 4096 genomes 4 -> 2 (N_max 64, C_max 256), 1024 shared "
                     "U(-1,1) samples, MSE against a fixed 4-32-2 tanh MLP; step = forward + "
                     "adjoint (dL/dW, dL/db)",
         "value": pop.P * 1024 / (step_ms * 1e-3), "unit": "sample-passes/s (forward+adjoint)",
-        "ms_per_step": step_ms, "roofline": {"bound": "hbm", "achieved": achieved,
-                                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                             "frac": achieved / HBM_PEAK_GBS,
-                                             "algorithmic_bytes": by},
+        "ms_per_step": step_ms, "roofline": _roof(by, lops, ms["forward_backward_mse"]),
     }
 
 
@@ -364,6 +473,16 @@ def hyperneat(torch, tn, synth, args):
         state["w"] = (w1t, w2t)
     steps = max(2, args.steps // 4)
     step_ms, ms = timed_steps(torch, step, steps, 1)
+    import numpy as np
+    nv, ne = genome_sizes(torch, pop, tr)
+    q = S * S + S * n_out
+    # per query: 5 inputs from the query index (about 6 lane-ops) + the CPPN's
+    # forward; the adjoint adds its reverse sweep (as the differentiation
+    # model) and the threshold test
+    fw = lane_ops_per_pass(pop, ne)
+    nodes = np.array([int(np.sum(pop.node_rows(g)["key"] >= pop.n_in)) for g in range(pop.P)])
+    q_lops = int((fw + 6).sum()) * q
+    b_lops = int((2 * fw + 6 * nodes + 2 * ne + 8).sum()) * q
     flops = 2.0 * pop.P * B * S * S + 2.0 * pop.P * B * S * n_out
     w_bytes = 2 * pop.P * (S * S + S * n_out)
     fwd_bytes = w_bytes + xb.numel() * 2 + 4 * pop.P * B * (S + n_out)
@@ -374,12 +493,133 @@ def hyperneat(torch, tn, synth, args):
                     "substrate backward + CPPN adjoint",
         "ms_per_step": step_ms, "call_ms": ms, "steps": steps,
         "queries_per_s": pop.P * (S * S + S * n_out) / (ms["cppn_query"] * 1e-3),
+        "cppn_query_roofline": _roof(2 * pop.P * q + 4 * pop.P * 16 * 32, q_lops,
+                                     ms["cppn_query"]),
+        "cppn_backward_roofline": _roof(4 * 2 * pop.P * q, b_lops, ms["cppn_backward"]),
         "substrate_forward": {
             "tflops": flops / (ms["substrate_forward"] * 1e-3) / 1e12,
             "mfma_frac": flops / (ms["substrate_forward"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
             "hbm_frac": fwd_bytes / (ms["substrate_forward"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "algorithmic_bytes": fwd_bytes},
     }
+
+
+# ------------------------------------------------------------------- xor
+
+def xor(torch, tn, synth, args):
+    pop = synth.xor_population()
+    dp = device_population(torch, tn, pop)
+    X = torch.from_numpy(synth.xor_inputs()).cuda()
+    T = torch.from_numpy(synth.xor_targets()).cuda()
+    tr = tn.Transformed(dp)
+
+    def step(t):
+        t("transform", tn.transform, dp, out=tr)
+        t("forward_loss", tn.forward_loss, dp, tr, X, T, -1.0, 4.0, False)
+    step_ms, ms = timed_steps(torch, step, max(args.steps, 50), args.warmup)
+    return {"workload": "xor: 150 genomes 3 -> 1 (N_max 16, C_max 32), the four XOR rows with "
+                        "bias input; step = transform + forward with the fused fitness 4 - SSE",
+            "us_per_call": 1e3 * step_ms, "call_us": {k: 1e3 * v for k, v in ms.items()},
+            "value": pop.P * 4 / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
+            "note": "launch-latency bound (two launches per call); the rooflines say nothing"}
+
+
+# ------------------------------------------------------------------ recurrent
+
+def recurrent(torch, tn, synth, args):
+    import numpy as np
+    pop = synth.recurrent_population()
+    B, T = 1000, 10
+    obs = torch.from_numpy(synth.normal_obs(pop.P, B, pop.n_in,
+                                            synth.CONFIG_SEEDS["recurrent"] + 100)).cuda()
+    dp = device_population(torch, tn, pop)
+    out = torch.empty((pop.P, B, pop.n_out), dtype=torch.float32, device="cuda")
+    step_ms, ms = timed_steps(torch, lambda t: t("recurrent", tn.forward_recurrent, dp, obs, T,
+                                                 out), args.steps, args.warmup)
+    ne = np.array([int(np.sum((pop.conn_rows(g)["in"] >= 0) & (pop.conn_rows(g)["en"] != 0)))
+                   for g in range(pop.P)])
+    lops = int(lane_ops_per_pass(pop, ne).sum()) * B * T
+    by = obs.numel() * 4 + out.numel() * 4 + pop.P * (14 * pop.N_max + 13 * pop.C_max)
+    return {"workload": "recurrent: 1000 genomes 17 -> 6 (control population plus up to 12 "
+                        "enabled back edges and self-loops each, N_max 64, C_max 256), 1000 "
+                        "N(0,1) observations per genome, 10 synchronous sweeps",
+            "value": pop.P * B / (step_ms * 1e-3), "unit": "genome-forward-passes/s",
+            "ms_per_step": step_ms, "roofline": _roof(by, lops, ms["recurrent"])}
+
+
+# ------------------------------------------------------------------ reproduce
+
+def reproduce(torch, tn, synth, args):
+    import numpy as np
+    pop = synth.control_population()
+    dp = device_population(torch, tn, pop)
+    n = pop.P
+    g = torch.Generator(device="cuda").manual_seed(11)
+    parents = torch.randint(0, pop.P, (n, 2), device="cuda", generator=g, dtype=torch.int32)
+    nu, nz = tn.reproduce_draws(pop.N_max, pop.C_max)
+    U = torch.rand((n, nu), device="cuda", generator=g)
+    Z = torch.randn((n, nz), device="cuda", generator=g)
+    next_key = int(max(pop.node_key.max(), pop.conn_in.max(), pop.conn_out.max())) + 1
+    step_ms, ms = timed_steps(torch, lambda t: t("reproduce", tn.reproduce, dp, parents, U, Z,
+                                                 None, next_key), args.steps, args.warmup)
+    row = 14 * pop.N_max + 13 * pop.C_max
+    by = n * (3 * row + 4 * (nu + nz) + 8)   # two parents read, the child written, draws
+    return {"workload": "reproduce: 1000 children of the control population (64 / 256 rows), "
+                        "random parent pairs, Appendix C rates; step = crossover + mutation "
+                        "with resident draws",
+            "value": n / (step_ms * 1e-3), "unit": "children/s", "ms_per_step": step_ms,
+            "roofline": {"bound": "hbm", "achieved": by / (ms["reproduce"] * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": by / (ms["reproduce"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes": by, "avg_ms": ms["reproduce"]}}
+
+
+# ------------------------------------------------------------- distance_nodes
+
+def distance_nodes(torch, tn, synth, args):
+    pop = synth.control_population()
+    dp = device_population(torch, tn, pop)
+    out = (torch.empty((pop.P, pop.P), dtype=torch.float32, device="cuda"),
+           torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"),
+           torch.empty((pop.P, pop.P), dtype=torch.int32, device="cuda"))
+    step_ms, ms = timed_steps(torch, lambda t: t("distance_nodes", tn.distance_nodes, dp, 1.0,
+                                                 0.5, True, out), args.steps, args.warmup)
+    return {"workload": "distance_nodes: 1000 x 1000 node-inclusive distance of the control "
+                        "population (c_d 1.0, c_h 0.5)",
+            "value": pop.P * pop.P / (step_ms * 1e-3), "unit": "pairs/s", "ms_per_step": step_ms}
+
+
+# ------------------------------------------------------------------- neat_xor
+
+def neat_xor(torch, tn, synth, args):
+    P, N, C = 150, 16, 32
+    prm = tn.NeatParams(mutation=tn.MutationParams(act_default=1))
+    nu, nz = tn.reproduce_draws(N, C)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    pop, table = tn.neat_init(P, 3, 1, N, C, torch.randn((P, nz), device="cuda", generator=g),
+                              prm.mutation, prm.max_species)
+    X = torch.from_numpy(synth.xor_inputs()).cuda()
+    T = torch.from_numpy(synth.xor_targets()).cuda()
+    state = {"pop": pop, "gen": 0, "key": 4, "best": []}
+
+    def step(t):
+        p = state["pop"]
+        fit, _ = t("fitness", lambda: tn.forward_loss(p, tn.transform(p), X, T, -1.0, 4.0, False))
+        sel = torch.rand((P, 2), device="cuda", generator=g)
+        U = torch.rand((P, nu), device="cuda", generator=g)
+        Z = torch.randn((P, nz), device="cuda", generator=g)
+        kids, _, _, nk = t("generation", tn.neat_generation, p, fit, state["gen"], table, sel, U,
+                           Z, state["key"], prm)
+        state["pop"], state["gen"] = kids, state["gen"] + 1
+        state["key"] += 2 * P   # an upper bound of the keys one generation can use
+        state["best"].append(fit)
+    step_ms, ms = timed_steps(torch, step, max(args.steps, 50), args.warmup)
+    best = [float(f.max()) for f in state["best"][-5:]]
+    return {"workload": "neat_xor: one NEAT generation on XOR, 150 genomes (16 / 32 rows), "
+                        "Appendix C parameters with sigmoid nodes; step = transform + fitness + "
+                        "speciation + counts + parents + reproduction (+ device draws)",
+            "value": 1e3 / step_ms, "unit": "generations/s", "ms_per_step": step_ms,
+            "call_ms": ms, "generations_run": state["gen"], "best_fitness_last": best}
 
 
 def main():
@@ -399,7 +639,9 @@ def main():
     others = {}
     if not args.only_headline:
         for name, fn in (("control", control), ("differentiation", differentiation),
-                         ("hyperneat", hyperneat)):
+                         ("hyperneat", hyperneat), ("xor", xor), ("recurrent", recurrent),
+                         ("reproduce", reproduce), ("distance_nodes", distance_nodes),
+                         ("neat_xor", neat_xor)):
             _log(f"workload {name}")
             others[name] = fn(torch, tn, synth, args)
             torch.cuda.empty_cache()
@@ -421,7 +663,10 @@ def main():
         "config": head["config"], "roofline": head["roofline"], "cpu_baseline": cpu,
         "plain_per_bucket": head["plain_per_bucket"],
         "whole_step_hbm_frac": head["whole_step_hbm_frac"],
+        "whole_step_alu_frac": head["whole_step_alu_frac"],
         "algorithmic_bytes_per_step": head["algorithmic_bytes_per_step"],
+        "lane_ops_per_step": head["lane_ops_per_step"],
+        "transform_plus_forward": head["transform_plus_forward"],
         "buckets": head["buckets"], "workloads": others,
     }
     print(json.dumps(line))
