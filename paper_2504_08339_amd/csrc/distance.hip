@@ -24,6 +24,7 @@ namespace {
 constexpr long long kPadKey = 0x7fffffffffffffffll;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t k) {
+  // lowbias32 (Chris Wellons' integer hash constants)
   k ^= k >> 16;
   k *= 0x7feb352du;
   k ^= k >> 15;

@@ -31,6 +31,7 @@ constexpr int32_t kEmptyKey = -1;
 constexpr unsigned long long kEmptyMark = ~0ull;
 
 __device__ __forceinline__ uint32_t hash32(uint32_t k) {
+  // lowbias32 (Chris Wellons' integer hash constants)
   k ^= k >> 16;
   k *= 0x7feb352du;
   k ^= k >> 15;
