@@ -1,5 +1,11 @@
-"""GPU parity of the HyperNEAT path (tn_cppn_query, tn_substrate_forward)
-against the float64 oracle.
+"""GPU parity of the HyperNEAT path (tn_cppn_query, tn_substrate_forward,
+tn_substrate_backward, tn_cppn_backward) against the float64 oracle. Every
+oracle input is synthetic or the oracle's own: substrate kernels get seeded
+synthetic bfloat16 weights, inputs and activations; threshold decisions on the
+oracle side are its own float64 ones, and where such a decision could differ
+from the GPU's float32 one (|w_ref| within the forward tolerance of the
+threshold: "ambiguous") the upstream gradient is set to 0 on both sides, or
+the bound carries the flip.
 
 CPPN values (before the threshold): the forward tolerance of test_gpu_forward,
 |w - w_ref| <= 1e-5 * cond + 2^-100. Stored weights: bit-exact round to
@@ -72,11 +78,16 @@ def _check_genome(pop, g, r1, r2, w1b, w2b):
         err = np.abs(raw.astype(np.float64) - ref)
         assert np.all(err <= tol), (g, float(err.max()))
         kept = np.where(np.abs(raw) < THR, np.float32(0), raw)
-        assert np.array_equal(wb, _bf16_bits(kept))
+        assert np.array_equal(wb, _bf16_bits(kept))   # consistency of the two outputs
         near = np.abs(np.abs(ref) - THR) <= tol
         ambiguous += int(near.sum())
         same = (np.abs(raw) < THR) == (np.abs(ref) < THR)
         assert np.all(same | near)
+        # the stored weight against the oracle's thresholded value: one bfloat16
+        # rounding (2^-8 relative) plus the float32 error, away from the threshold
+        want = hn.threshold(ref, THR)
+        diff = np.abs(_bf16_value(wb) - want)
+        assert np.all((diff <= 2.0 ** -8 * np.abs(want) + tol) | near), g
     return ambiguous
 
 
@@ -116,104 +127,65 @@ def test_cppn_query_flagged_and_shape_errors():
     assert np.all(host(dW)[0] == 0.0) and np.all(host(db)[0] == 0.0)
 
 
-def _substrate_case(P, B, shared):
-    tn, pop, dp, tr, w1t, w2t = _query(P, seed=15)[:6]
-    rng = np.random.default_rng(8)
-    X = rng.standard_normal((B, GRID * GRID) if shared else (P, B, GRID * GRID)).astype(np.float32)
-    xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
-    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
-    return tn, pop, w1t, w2t, xb, host(h), host(y)
+def _synthetic_weights(P, seed):
+    """Seeded bfloat16 substrate weights, about half zero (as after a
+    threshold), as device tensors of bfloat16 bits and their float64 values."""
+    rng = np.random.default_rng(seed)
+    S = GRID * GRID
+    w1 = rng.standard_normal((P, S, S)).astype(np.float32) * np.float32(0.05)
+    w1[rng.random(w1.shape) < 0.5] = 0.0
+    w2 = rng.standard_normal((P, NOUT, S)).astype(np.float32) * np.float32(0.05)
+    b1, b2 = _bf16_bits(w1), _bf16_bits(w2)
+    t1 = torch.from_numpy(b1.view(np.int16)).cuda().view(torch.bfloat16)
+    t2 = torch.from_numpy(b2.view(np.int16)).cuda().view(torch.bfloat16)
+    return t1, t2, _bf16_value(b1), _bf16_value(b2)
+
+
+def _bf16_input(shape, seed):
+    X = np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+    bits = _bf16_bits(X)
+    return torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16), _bf16_value(bits)
 
 
 @pytest.mark.parametrize("shared", [True, False])
-def test_substrate_forward_matches_oracle_on_gpu_weights(shared):
-    tn, pop, w1t, w2t, xb, h, y = _substrate_case(4, 100, shared)
-    W1 = _bf16_value(_bits16(w1t))          # [P][t][s]
-    W2 = _bf16_value(_bits16(w2t))          # [P][j][t]
-    Xv = _bf16_value(_bits16(xb))
-    for g in range(pop.P):
-        Xg = Xv if shared else Xv[g]
-        Z = Xg @ W1[g].T
-        S1 = np.abs(Xg) @ np.abs(W1[g]).T
-        assert np.all(np.abs(h[g] - np.tanh(Z)) <= 2.0 ** -14 * S1 + 2.0 ** -21), g
-        Hb = _bf16_value(_bf16_bits(h[g]))
-        ref = Hb @ W2[g].T
-        bound = 2.0 ** -14 * (np.abs(Hb) @ np.abs(W2[g]).T) + 1e-30
-        assert np.all(np.abs(y[g] - ref) <= bound), g
-
-
-def test_substrate_end_to_end_against_float64():
-    """GPU outputs against the float64 pipeline (float64 CPPN weights with the
-    GPU's threshold decisions, float64 inputs, no rounding)."""
-    tn, pop, dp, tr, w1t, w2t, r1, r2 = _query(3, seed=25)
-    rng = np.random.default_rng(9)
-    X = rng.standard_normal((64, GRID * GRID)).astype(np.float32)
-    xb = torch.from_numpy(X).cuda().to(torch.bfloat16)
-    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
-    y = host(y)
-    r1, r2 = host(r1), host(r2)
-    grid, outs = hn.grid_coords(GRID), hn.row_coords(NOUT)
-    for g in range(pop.P):
-        gen = oracle.decode(pop, g)
-        otr = oracle.transform(gen)
-        raw1 = hn.cppn_weights(gen, otr, grid, grid)      # [s][t]
-        raw2 = hn.cppn_weights(gen, otr, grid, outs)
-        W1 = np.where(np.abs(r1[g].T) < THR, 0.0, raw1)   # the GPU's decisions
-        W2 = np.where(np.abs(r2[g].T) < THR, 0.0, raw2)
-        H, Y = hn.substrate_forward(X.astype(np.float64), W1, W2)
-        scale = hn.error_scale(X.astype(np.float64), W1, W2, H)
-        assert np.all(np.abs(y[g] - Y) <= 2.0 ** -7 * scale), g
-
-
-def test_full_size_sampled():
-    """1000 CPPNs on the 32 x 32 / 32 x 32 / 8 substrate with 128 inputs per
-    genome, as the benchmark runs it; two sampled genomes against the oracle."""
+def test_substrate_forward_matches_oracle(shared):
+    """h against tanh(X W1) in float64 on the same bfloat16 values (float32
+    accumulation of K = 1024 exact products: 2^-14 of the magnitudes, plus
+    tanh's 2^-21); y against the oracle's bf16(H) W2, where the GPU rounds its
+    own float32 h: the two roundings can differ by one bfloat16 step per term
+    (2^-8 of |H| |W2|) besides the accumulation's 2^-14."""
     import paper_2504_08339_amd as tn
-    pop = synth.cppn_population()
-    dp = to_device(pop)
-    tr = tn.transform(dp)
-    w1t, w2t = tn.cppn_query(dp, tr, GRID, NOUT, THR)
-    X = torch.randn((pop.P, 128, GRID * GRID), generator=torch.Generator().manual_seed(5))
-    xb = X.cuda().to(torch.bfloat16)
+    P, B = 4, 100
+    w1t, w2t, W1, W2 = _synthetic_weights(P, 15)
+    xb, Xv = _bf16_input((B, GRID * GRID) if shared else (P, B, GRID * GRID), 8)
     h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
-    torch.cuda.synchronize()
-    yh = host(y)
-    assert np.isfinite(yh).all()
-    W1 = w1t.float()
-    W2 = w2t.float()
-    Xv = xb.float()
-    for g in (17, 803):
-        ref = torch.tanh(Xv[g].double() @ W1[g].double().T)
-        assert torch.all((h[g].double() - ref).abs() <= 2.0 ** -14 * (Xv[g].double().abs() @ W1[g].double().abs().T) + 2.0 ** -21)
-        Hb = h[g].to(torch.bfloat16).double()
-        refy = Hb @ W2[g].double().T
-        assert torch.all((y[g].double() - refy).abs() <= 2.0 ** -14 * (Hb.abs() @ W2[g].double().abs().T) + 1e-30)
-        # the sampled weights against the oracle's CPPN
-        gen = oracle.decode(pop, g)
-        otr = oracle.transform(gen)
-        src = hn.grid_coords(GRID)[::97]
-        ref_w = hn.cppn_weights(gen, otr, src, hn.grid_coords(GRID))    # [s][t]
-        got = W1[g][:, ::97].cpu().numpy().T                          # [s][t]
-        ok = (np.abs(np.abs(ref_w) - THR) > 1e-4)
-        expect = _bf16_value(_bf16_bits(hn.threshold(ref_w).astype(np.float32)))
-        assert np.all((np.abs(got - expect) <= 2.0 ** -7 * np.abs(expect)) | ~ok)   # one bf16 step
+    h, y = host(h), host(y)
+    for g in range(P):
+        Xg = Xv if shared else Xv[g]
+        H, _ = hn.substrate_forward(Xg, W1[g].T, W2[g].T)
+        S1 = np.abs(Xg) @ np.abs(W1[g]).T
+        assert np.all(np.abs(h[g] - H) <= 2.0 ** -14 * S1 + 2.0 ** -21), g
+        Hb = _bf16_value(_bf16_bits(H.astype(np.float32)))
+        mag = np.abs(Hb) @ np.abs(W2[g]).T
+        assert np.all(np.abs(y[g] - Hb @ W2[g].T) <= (2.0 ** -8 + 2.0 ** -14) * mag + 1e-30), g
 
 
 @pytest.mark.parametrize("shared", [True, False])
 def test_substrate_backward_matches_oracle(shared):
-    """Gradients of sum(dY * Y) against the oracle's substrate adjoint computed
-    from the GPU's own h, weights and inputs. dw2t: float32 sums of B <= 128
+    """Gradients of sum(dY * Y) against the oracle's substrate adjoint on the
+    same synthetic h, dY, weights and inputs. dw2t: float32 sums of B <= 128
     terms, |err| <= 2^-17 * sum_b |h dy|; dw1t: dZ rounded to bfloat16 (2^-9)
     plus float32 accumulation, |err| <= 2^-8 * sum_b |dz_b x_b|."""
     import paper_2504_08339_amd as tn
     P, B = 3, 100
-    _, pop, w1t, w2t, xb, h, y = _substrate_case(P, B, shared)
-    dy = np.random.default_rng(12).standard_normal((P, B, NOUT)).astype(np.float32)
+    _, w2t, _, W2 = _synthetic_weights(P, 16)
+    xb, Xv = _bf16_input((B, GRID * GRID) if shared else (P, B, GRID * GRID), 9)
+    rng = np.random.default_rng(12)
+    h = np.tanh(rng.standard_normal((P, B, GRID * GRID))).astype(np.float32)
+    dy = rng.standard_normal((P, B, NOUT)).astype(np.float32)
     dw1t, dw2t = tn.substrate_backward(w2t, xb, torch.from_numpy(h).cuda(),
                                        torch.from_numpy(dy).cuda(), GRID, NOUT, THR)
     dw1t, dw2t = host(dw1t), host(dw2t)
-    W2 = _bf16_value(_bits16(w2t))          # [P][j][t]
-    Xv = _bf16_value(_bits16(xb))
     for g in range(P):
         Xg = Xv if shared else Xv[g]
         H = h[g].astype(np.float64)
@@ -226,34 +198,134 @@ def test_substrate_backward_matches_oracle(shared):
         assert np.all(np.abs(dw1t[g].T - dW1) <= b1), g
 
 
+def _oracle_raw(gen, tr, src, dst):
+    """The oracle's CPPN values [S][T] and the mask of ambiguous threshold
+    decisions (|w| within the forward tolerance of the threshold)."""
+    ref, cond = oracle.forward(gen, tr, hn.query_inputs(src, dst), with_cond=True)
+    ref = ref[:, 0].reshape(len(src), len(dst))
+    cond = cond[:, 0].reshape(len(src), len(dst))
+    return ref, np.abs(np.abs(ref) - THR) <= 1e-5 * cond + 2.0 ** -100
+
+
+def _flip_bound(A1, A2, X, W2, H, tol1, tol2):
+    """How far the outputs can move when the ambiguous threshold decisions
+    (masks A1 [s][t], A2 [t][j]) go the other way: a weight flips between 0 and
+    at most thr + its tolerance; tanh' <= 1."""
+    dz = np.abs(X) @ (A1 * (THR + tol1))                          # [B][t]
+    return dz @ np.abs(W2) + np.abs(H) @ (A2 * (THR + tol2))     # [B][j]
+
+
+def _oracle_pipeline(pop, g, grid, n_out, X):
+    """The oracle's own substrate for genome g: float64 weights with its own
+    threshold decisions, H, Y, the error scale and the flip bound."""
+    gen = oracle.decode(pop, g)
+    otr = oracle.transform(gen)
+    src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    ref1, cond1 = oracle.forward(gen, otr, hn.query_inputs(src, src), with_cond=True)
+    ref2, cond2 = oracle.forward(gen, otr, hn.query_inputs(src, outs), with_cond=True)
+    S = grid * grid
+    r1, c1 = ref1[:, 0].reshape(S, S), cond1[:, 0].reshape(S, S)
+    r2, c2 = ref2[:, 0].reshape(S, n_out), cond2[:, 0].reshape(S, n_out)
+    t1, t2 = 1e-5 * c1 + 2.0 ** -100, 1e-5 * c2 + 2.0 ** -100
+    A1, A2 = np.abs(np.abs(r1) - THR) <= t1, np.abs(np.abs(r2) - THR) <= t2
+    W1, W2 = hn.threshold(r1, THR), hn.threshold(r2, THR)
+    H, Y = hn.substrate_forward(X, W1, W2)
+    return W1, W2, H, Y, hn.error_scale(X, W1, W2, H), _flip_bound(A1, A2, X, W2, H, t1, t2)
+
+
+def test_substrate_end_to_end_against_float64():
+    """GPU query + substrate forward against the oracle's float64 pipeline
+    with its own threshold decisions: |y - y_ref| <= 2^-7 * error_scale (the
+    four bfloat16 roundings take 2^-8 of it, pinned in test_oracle_hyperneat;
+    accumulation and the CPPN's float32 error stay in the rest) + the effect of
+    the ambiguous decisions."""
+    tn, pop, dp, tr, w1t, w2t, r1, r2 = _query(3, seed=25)
+    xb, Xv = _bf16_input((64, GRID * GRID), 9)
+    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
+    y = host(y)
+    for g in range(pop.P):
+        W1, W2, H, Y, scale, flip = _oracle_pipeline(pop, g, GRID, NOUT, Xv)
+        assert np.all(np.abs(y[g] - Y) <= 2.0 ** -7 * scale + flip), g
+
+
+def test_full_size_sampled():
+    """1000 CPPNs on the 32 x 32 / 32 x 32 / 8 substrate with 128 inputs per
+    genome, as the benchmark runs it; three sampled genomes against the
+    oracle's own pipeline (hidden values: one bfloat16 rounding of each weight,
+    2^-8, and float32 accumulation, 2^-14, of sum |x w|, plus the ambiguous
+    decisions; outputs: the end-to-end bound)."""
+    import paper_2504_08339_amd as tn
+    pop = synth.cppn_population()
+    dp = to_device(pop)
+    tr = tn.transform(dp)
+    w1t, w2t = tn.cppn_query(dp, tr, GRID, NOUT, THR)
+    xb, Xv = _bf16_input((pop.P, 128, GRID * GRID), 5)
+    h, y = tn.substrate_forward(w1t, w2t, xb, GRID, NOUT, THR)
+    h, y = host(h), host(y)
+    assert np.isfinite(y).all()
+    for g in (17, 500, 803):
+        W1, W2, H, Y, scale, flip = _oracle_pipeline(pop, g, GRID, NOUT, Xv[g])
+        mag = np.abs(Xv[g]) @ np.abs(W1)
+        src = hn.grid_coords(GRID)
+        gen = oracle.decode(pop, g)
+        ref1, cond1 = oracle.forward(gen, oracle.transform(gen), hn.query_inputs(src, src),
+                                     with_cond=True)
+        t1 = 1e-5 * cond1[:, 0].reshape(GRID * GRID, GRID * GRID) + 2.0 ** -100
+        A1 = np.abs(np.abs(ref1[:, 0].reshape(GRID * GRID, GRID * GRID)) - THR) <= t1
+        dz = np.abs(Xv[g]) @ (A1 * (THR + t1))
+        assert np.all(np.abs(h[g] - H) <= (2.0 ** -8 + 2.0 ** -14) * mag + dz + 2.0 ** -21), g
+        assert np.all(np.abs(y[g] - Y) <= 2.0 ** -7 * scale + flip), g
+        print(f"genome {g}: ambiguous threshold decisions {int(A1.sum())}, "
+              f"max |y - y64| / scale {float(np.max(np.abs(y[g] - Y) / scale)):.3e}")
+
+
 def _cppn_grad_case(grid, n_out, P, seed):
+    """Upstream gradients drawn from a seed, set to 0 at the queries whose
+    threshold decision is ambiguous by the oracle's own values, fed to both
+    sides."""
     import paper_2504_08339_amd as tn
     pop = synth.cppn_population(seed=seed, P=P)
     dp = to_device(pop)
     tr = tn.transform(dp)
-    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
     S = grid * grid
     rng = np.random.default_rng(seed)
-    u1 = rng.standard_normal((P, S, S)).astype(np.float32)
-    u2 = rng.standard_normal((P, n_out, S)).astype(np.float32)
+    u1 = rng.standard_normal((P, S, S)).astype(np.float32)      # [g][t][s]
+    u2 = rng.standard_normal((P, n_out, S)).astype(np.float32)  # [g][j][s]
+    src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    raws = []
+    for g in range(P):
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        if otr.status:
+            raws.append(None)
+            continue
+        r1, a1 = _oracle_raw(gen, otr, src, src)      # [s][t]
+        r2, a2 = _oracle_raw(gen, otr, src, outs)
+        u1[g][a1.T] = 0.0
+        u2[g][a2.T] = 0.0
+        raws.append((r1, r2))
     dW, db = tn.cppn_backward(dp, tr, torch.from_numpy(u1).cuda(), torch.from_numpy(u2).cuda(),
                               grid, n_out, THR)
-    return pop, host(r1), host(r2), u1, u2, host(dW), host(db)
+    return pop, raws, u1, u2, host(dW), host(db)
 
 
-def _check_cppn_grads(pop, grid, n_out, r1, r2, u1, u2, dW, db, genomes):
-    """Against the oracle's CPPN adjoint with the GPU's threshold decisions:
-    |g - g_ref| <= 1e-4 |g_ref| + 1e-5 max|g_ref| per genome (float32 sums
-    over up to 2^20 queries of terms that carry the forward's 1e-5 error)."""
+def _check_cppn_grads(pop, grid, n_out, raws, u1, u2, dW, db, genomes):
+    """Against the oracle's CPPN adjoint with its own threshold decisions:
+    |g - g_ref| <= 3e-5 |g_ref| + 1e-5 max|g_ref| per genome (float32 sums
+    over up to 2^20 queries of terms that carry the forward's 1e-5 error; the
+    worst measured |g - g_ref| / (|g_ref| + max|g_ref|) is 6.4e-6 on the full
+    substrate, 1.1e-6 on the small one); returns that worst ratio."""
     src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    worst = 0.0
     for g in genomes:
         gen = oracle.decode(pop, g)
         tr = oracle.transform(gen)
         if tr.status:
             assert np.isnan(dW[g]).all() and np.isnan(db[g]).all()
             continue
-        a = hn.cppn_gradient(gen, tr, src, src, r1[g].T, u1[g].T.astype(np.float64))
-        b = hn.cppn_gradient(gen, tr, src, outs, r2[g].T, u2[g].T.astype(np.float64))
+        r1, r2 = raws[g]
+        a = hn.cppn_gradient(gen, tr, src, src, r1, u1[g].T.astype(np.float64))
+        b = hn.cppn_gradient(gen, tr, src, outs, r2, u2[g].T.astype(np.float64))
         ref_w = np.zeros(pop.C_max)
         ref_b = np.zeros(pop.N_max)
         for row, val in a[0].items():
@@ -262,21 +334,26 @@ def _check_cppn_grads(pop, grid, n_out, r1, r2, u1, u2, dW, db, genomes):
             ref_b[row] += val + b[1][row]
         ref = np.concatenate([ref_w, ref_b])
         got = np.concatenate([dW[g], db[g]]).astype(np.float64)
-        tol = 1e-4 * np.abs(ref) + 1e-5 * np.abs(ref).max()
-        assert np.all(np.abs(got - ref) <= tol), (g, float(np.max(np.abs(got - ref) - tol)))
+        err = np.abs(got - ref)
+        tol = 3e-5 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+        assert np.all(err <= tol), (g, float(np.max(err - tol)))
+        worst = max(worst, float(np.max(err / (np.abs(ref) + np.abs(ref).max() + 1e-300))))
+    return worst
 
 
 def test_cppn_backward_small_grid():
-    pop, r1, r2, u1, u2, dW, db = _cppn_grad_case(8, 2, 8, 31)
-    _check_cppn_grads(pop, 8, 2, r1, r2, u1, u2, dW, db, range(pop.P))
+    pop, raws, u1, u2, dW, db = _cppn_grad_case(8, 2, 8, 31)
+    worst = _check_cppn_grads(pop, 8, 2, raws, u1, u2, dW, db, range(pop.P))
+    print(f"CPPN adjoint, 8x8 substrate: worst |err| / (|g| + max|g|) {worst:.3e}")
     dead = (pop.conn_in < 0) | (pop.conn_en == 0)
     assert np.all(dW[dead] == 0.0)
     assert np.all(db[pop.node_key < pop.n_in] == 0.0)
 
 
 def test_cppn_backward_full_substrate():
-    pop, r1, r2, u1, u2, dW, db = _cppn_grad_case(GRID, NOUT, 2, 41)
-    _check_cppn_grads(pop, GRID, NOUT, r1, r2, u1, u2, dW, db, range(pop.P))
+    pop, raws, u1, u2, dW, db = _cppn_grad_case(GRID, NOUT, 2, 41)
+    worst = _check_cppn_grads(pop, GRID, NOUT, raws, u1, u2, dW, db, range(pop.P))
+    print(f"CPPN adjoint, 32x32 substrate: worst |err| / (|g| + max|g|) {worst:.3e}")
 
 
 def test_cppn_backward_both_slot_forms_and_edge_limit():
@@ -294,35 +371,64 @@ def test_cppn_backward_both_slot_forms_and_edge_limit():
     grid, n_out = 8, 2
     dp = to_device(pop)
     tr = tn.transform(dp)
-    _, _, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
     S = grid * grid
     u1 = rng.standard_normal((pop.P, S, S)).astype(np.float32)
     u2 = rng.standard_normal((pop.P, n_out, S)).astype(np.float32)
+    src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    raws = []
+    for g in range(pop.P):
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        r1, a1 = _oracle_raw(gen, otr, src, src)
+        r2, a2 = _oracle_raw(gen, otr, src, outs)
+        u1[g][a1.T] = 0.0
+        u2[g][a2.T] = 0.0
+        raws.append((r1, r2))
     dW, db = tn.cppn_backward(dp, tr, torch.from_numpy(u1).cuda(), torch.from_numpy(u2).cuda(),
                               grid, n_out, THR)
     dW, db = host(dW), host(db)
     over = [g for g in range(pop.P) if edges[g] > 64]
     for g in over:
         assert np.isnan(dW[g]).all() and np.isnan(db[g]).all()
-    _check_cppn_grads(pop, grid, n_out, host(r1), host(r2), u1, u2, dW, db,
+    _check_cppn_grads(pop, grid, n_out, raws, u1, u2, dW, db,
                       [g for g in range(pop.P) if edges[g] <= 64])
 
 
 def test_cppn_backward_through_the_substrate():
-    """The whole chain: CPPN query -> substrate forward -> substrate backward ->
-    CPPN adjoint, against the oracle's pipeline gradient (with the GPU's
-    threshold decisions and the GPU's substrate gradients as upstream)."""
+    """The whole chain on the GPU (CPPN query -> substrate forward -> substrate
+    backward -> CPPN adjoint) against the oracle's float64 chain with its own
+    decisions. The genomes and inputs are chosen so that no threshold decision
+    is ambiguous (checked on the oracle side); the GPU's bfloat16 weights,
+    inputs and dZ put a few 2^-8 on the substrate gradients, so the CPPN
+    gradient is held to 2^-5 of the genome's largest component."""
     import paper_2504_08339_amd as tn
-    pop = synth.cppn_population(seed=51, P=2)
+    pop = synth.cppn_population(seed=54, P=2)
+    grid, n_out = 8, 4
+    src, outs = hn.grid_coords(grid), hn.row_coords(n_out)
+    for g in range(pop.P):
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        assert not _oracle_raw(gen, otr, src, src)[1].any()
+        assert not _oracle_raw(gen, otr, src, outs)[1].any()
     dp = to_device(pop)
     tr = tn.transform(dp)
-    grid, n_out = 8, 4
-    w1t, w2t, r1, r2 = tn.cppn_query(dp, tr, grid, n_out, THR, raw=True)
-    rng = np.random.default_rng(6)
-    xb = torch.from_numpy(rng.standard_normal((32, grid * grid)).astype(np.float32)).cuda().to(torch.bfloat16)
+    w1t, w2t = tn.cppn_query(dp, tr, grid, n_out, THR)
+    xb, Xv = _bf16_input((32, grid * grid), 6)
     h, y = tn.substrate_forward(w1t, w2t, xb, grid, n_out)
-    dy = torch.from_numpy(rng.standard_normal((2, 32, n_out)).astype(np.float32)).cuda()
-    dw1t, dw2t = tn.substrate_backward(w2t, xb, h, dy, grid, n_out)
+    dyn = np.random.default_rng(6).standard_normal((2, 32, n_out)).astype(np.float32)
+    dw1t, dw2t = tn.substrate_backward(w2t, xb, h, torch.from_numpy(dyn).cuda(), grid, n_out)
     dW, db = tn.cppn_backward(dp, tr, dw1t, dw2t, grid, n_out)
-    _check_cppn_grads(pop, grid, n_out, host(r1), host(r2), host(dw1t), host(dw2t), host(dW),
-                      host(db), range(pop.P))
+    dW, db = host(dW), host(db)
+    for g in range(pop.P):
+        gen = oracle.decode(pop, g)
+        otr = oracle.transform(gen)
+        ref = hn.hyperneat(gen, otr, grid, n_out, Xv, dyn[g].astype(np.float64), THR)
+        rw = np.zeros(pop.C_max)
+        rb = np.zeros(pop.N_max)
+        for r, v in ref["dw_cppn"].items():
+            rw[r] = v
+        for r, v in ref["db_cppn"].items():
+            rb[r] = v
+        want = np.concatenate([rw, rb])
+        got = np.concatenate([dW[g], db[g]]).astype(np.float64)
+        assert np.all(np.abs(got - want) <= 2.0 ** -5 * np.abs(want).max() + 1e-12), g
