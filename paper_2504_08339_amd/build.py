@@ -125,5 +125,43 @@ def build(verbose: bool = False, extra=()) -> str:
     return LIB
 
 
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
+            "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """Every csrc/*.hip with AddressSanitizer and UndefinedBehaviorSanitizer on
+    the host code only (argument checks, plan bookkeeping, workspace carving;
+    the device code is the product's), linked into
+    _build/sanitize/libtnhip_host_san.so, for host-only tests on the CPU."""
+    out_dir = os.path.join(BUILD, "sanitize")
+    os.makedirs(out_dir, exist_ok=True)
+    flags = [*COMMON, "-Xarch_host", "-g", *SANITIZE]
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        cmd = [hipcc(), *flags, "-c", src, "-o", obj]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{res.stderr}")
+        return obj
+
+    srcs = sources()
+    with cf.ThreadPoolExecutor(min(8, len(srcs))) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libtnhip_host_san.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *SANITIZE, "-o", lib, *objs]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stderr}")
+    if verbose:
+        print(f"built {lib}", file=sys.stderr)
+    return lib
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "--host-sanitized":
+        build_host_sanitized(verbose=True)
+    else:
+        build(verbose=True)
