@@ -297,13 +297,22 @@ int tn_forward_loss(const tn_population* pop, const tn_transformed* tr, const fl
   rc = check_transformed(tr);
   if (rc != TN_OK) return rc;
   if (!loss || (B > 0 && !target)) return TN_EINVAL;
-  const bool split = pop->N_max > 64;
-  rc = tn::launch_forward_loss_reg(*pop, *tr, obs, obs_genome_stride, B, target,
-                                   target_genome_stride, scale, offset, out, loss, 4, split,
-                                   stream);
-  if (rc != TN_OK || !split) return rc;
+  // the register files of the automatic choice, smallest first (each taking
+  // the genomes the smaller ones could not; prog_rows <= N_max, so a small
+  // population needs one launch), then the LDS engine above 200 rows
+  int cls[6];
+  const int n = tn::reg_classes(B, cls);
+  int lo = -1;
+  for (int i = 0; i < n; ++i) {
+    rc = tn::launch_forward_loss_reg(*pop, *tr, obs, obs_genome_stride, B, target,
+                                     target_genome_stride, scale, offset, out, loss, 4, cls[i],
+                                     lo, pop->N_max > cls[i], stream);
+    if (rc != TN_OK || pop->N_max <= cls[i]) return rc;
+    lo = cls[i];
+  }
   return tn::launch_forward_loss(*pop, *tr, obs, obs_genome_stride, B, target,
-                                 target_genome_stride, scale, offset, out, loss, 64, stream);
+                                 target_genome_stride, scale, offset, out, loss, tn::kRegRowsMax,
+                                 stream);
 }
 
 int tn_backward(const tn_population* pop, const tn_transformed* tr, const float* obs,

@@ -1,17 +1,16 @@
 // Calculation stage (TensorNEAT Section 3.3) for genomes whose forward pass
-// needs at most 64 value rows, with every node value held in registers.
+// needs at most 200 value rows, with every node value held in registers.
 //
-// Mapping: one wavefront per tile of 64 observations of one genome (lane =
-// observation); a workgroup holds W wavefronts of the same genome, so that the
-// genome's packed program (tn_transformed.prog_node / prog_edge) is fetched
-// into the compute unit's scalar cache once. The program is read with scalar
-// loads and every loop and branch over it is wavefront uniform. A lane's node
-// values live in one or two 32-entry register banks addressed with a uniform
-// index (s_set_gpr_idx), so an in-edge costs one indexed register read and one
-// fused multiply-add: no LDS traffic and no barrier in the evaluation. The
-// value rows are the packed program's rows (freed right after their last
-// read; input k sits in row k). Observations are read coalesced and transposed
-// through a small per-wavefront LDS buffer; outputs leave the same way.
+// Mapping: one wavefront per unit of 64, 128 or 256 observations of one genome
+// (lane = observation of each tile of the unit); a workgroup holds W
+// wavefronts. A lane's node values live in an explicit register file (rows at
+// fixed VGPRs, fwd_reg.hpp) addressed with a uniform index window, so an
+// in-edge is one indexed fused multiply-add: no LDS traffic and no barrier in
+// the evaluation. The value rows are the packed program's rows (freed right
+// after their last read; input k sits in row k). Observations are staged
+// through a small per-wavefront LDS buffer (LDS-direct loads); outputs leave
+// through it or straight from the registers. With a loss, one workgroup per
+// genome shares its units and reduces the squared error in a fixed order.
 #include <algorithm>
 
 #include "fwd_launch.hpp"
@@ -35,7 +34,7 @@ struct RegArgs {
   const int32_t* genomes;  // genome list (nullptr: every genome, in order)
   int32_t* queue;          // persistent form: next item to take
   int n_items;             // grid form: list length * n_groups; persistent: * n_tiles
-  int in_phase;            // register file: tiles of inputs staged per LDS-direct round (0: chunks)
+  int in_phase;            // tiles of inputs staged per LDS-direct round
   int stage_stride;        // floats of LDS staging per wavefront
   int n_list;              // persistent form: list length
 };
@@ -55,8 +54,8 @@ __device__ __forceinline__ int share_items(int n_list, int x, int units) {
 // per-lane row accesses are free of bank conflicts.
 constexpr int kChunk = 8;
 constexpr int kStage = kWave * (kChunk + 1);  // floats per tile
-// staging regions per wavefront of variant V
-constexpr int stage_tiles(int V) { return V >= 32 ? rf_tiles(V) : 1; }
+// staging regions per wavefront of variant V (its tiles per unit)
+constexpr int stage_tiles(int V) { return rf_tiles(V); }
 
 // The register-file form stages a unit's observations with LDS-direct loads
 // (global_load_lds: memory to LDS without passing through registers, so a
@@ -67,10 +66,8 @@ constexpr int stage_tiles(int V) { return V >= 32 ? rf_tiles(V) : 1; }
 // SIMD then still fit the compute unit's LDS), one tile per round at least.
 constexpr int kDmaBytes = 20 * 1024;
 
-// Tiles per LDS-direct round for variant V and I inputs (0: the bank forms,
-// which stage in chunks of kChunk columns through registers).
+// Tiles per LDS-direct round for variant V and I inputs.
 int dma_phase(int V, int I) {
-  if (V < 32) return 0;
   int P = rf_tiles(V);
   while (P > 1 && (int64_t)P * kWave * I * 4 > kDmaBytes) P /= 2;
   return P;
@@ -108,71 +105,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   const int full = per * kXcd;
   if (bid >= full) return bid;
   return (bid % kXcd) * per + bid / kXcd;
-}
-
-// One tile of 64 observations: input rows from the staging buffer, program
-// walk, output rows back to the staging buffer, chunk by chunk.
-template <int NB, bool kLoss>
-__device__ __forceinline__ float run_tile(const int4* __restrict__ pn,
-                                          const int2* __restrict__ pe,
-                                          const int32_t* __restrict__ out_pos, int orow_first,
-                                          int n, int I, int O, int nbat,
-                                          const float* __restrict__ xo, float* __restrict__ yo,
-                                          const float* __restrict__ to, float* stg, int lane) {
-  // The banks start at zero in every tile; the empty asm keeps the compiler
-  // from hoisting that out of the tile loop (which would keep both banks of
-  // every variant live across it).
-  f32x32 lo = 0.0f, hi = 0.0f;
-  if constexpr (NB < 32) asm volatile("" : "+v"(lo));
-  if constexpr (NB == 2) asm volatile("" : "+v"(hi));
-  // inputs: coalesced loads of the tile's rows, transposed through LDS
-  for (int c0 = 0; c0 < I; c0 += kChunk) {
-    const int ch = min(kChunk, I - c0);
-    const int sr = ch | 1;
-    const int tot = nbat * ch;
-    DivWalk dw(lane, ch, kWave);
-    for (int i0 = 0; i0 < tot; i0 += 8 * kWave) {
-      float t[8];
-      int o[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const bool ok = i0 + u * kWave + lane < tot;
-        o[u] = ok ? dw.b * sr + dw.c : -1;
-        t[u] = ok ? xo[(int64_t)dw.b * I + c0 + dw.c] : 0.0f;
-        dw.step();
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (o[u] >= 0) stg[o[u]] = t[u];
-    }
-    wave_sync();
-    for (int j = 0; j < ch; ++j) vset<NB>(lo, hi, c0 + j, stg[lane * sr + j]);
-    wave_sync();
-  }
-  walk_program<NB>(lo, hi, pn, pe, n);
-  // outputs
-  float sse = 0.0f;
-  for (int c0 = 0; c0 < O; c0 += kChunk) {
-    const int ch = min(kChunk, O - c0);
-    const int sr = ch | 1;
-    const int orow = c0 == 0 ? orow_first : (lane < ch ? prog_row(pn, out_pos[c0 + lane]) : 0);
-    for (int j = 0; j < ch; ++j) stg[lane * sr + j] = vget<NB>(lo, hi, __builtin_amdgcn_readlane(orow, j));
-    wave_sync();
-    const int tot = nbat * ch;
-    DivWalk dw(lane, ch, kWave);
-    for (int i = lane; i < tot; i += kWave) {
-      const float y = stg[dw.b * sr + dw.c];
-      const int64_t at = (int64_t)dw.b * O + c0 + dw.c;
-      if (yo) yo[at] = y;
-      if (kLoss) {
-        const float d = y - to[at];
-        sse = fmaf(d, d, sse);
-      }
-      dw.step();
-    }
-    wave_sync();
-  }
-  return sse;
 }
 
 // One unit of the register-file engine: rf_tiles(R) consecutive tiles of 64
@@ -303,7 +235,6 @@ __device__ __forceinline__ float run_unit(const int32_t* __restrict__ rec,
 // Tiles t_begin, t_begin + t_step, ... < t_end of genome g by this wavefront;
 // returns its part of the squared error (kLoss). *st_out: the genome's
 // status as the launch sees it (0: evaluated; -2: left to another launch).
-// NB = 0 picks one or two register banks from the genome's prog_rows.
 template <int NB, bool kLoss>
 __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, int t_end,
                                             int t_step, float* stg, int* st_out) {
@@ -325,8 +256,7 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
   const int nn = n - I;
   const int32_t* out_pos = io_pos + (int64_t)g * nio + I;
   const int orow_first = !st && lane < min(O, kChunk) ? prog_row(pn, out_pos[lane]) : 0;
-  const bool one_bank = NB == 1 || (NB == 0 && rows <= 32);
-  constexpr int K = NB >= 32 ? rf_tiles(NB) : 1;
+  constexpr int K = rf_tiles(NB);
   float sse = 0.0f;
   for (int t = t_begin; t < t_end; t += t_step) {
     const int b0 = t * K * kWave;
@@ -339,18 +269,8 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
     }
     const float* xg = obs + (int64_t)g * a.obs_stride;
     const float* tg = kLoss ? target + (int64_t)g * a.target_stride : nullptr;
-    if constexpr (NB >= 32) {
-      sse += run_unit<NB, kLoss>(rec, pe, nn, a.in_phase, pn, out_pos, orow_first, I, O, b0, a.B, xg, yg,
-                                 tg, stg, lane);
-    } else {
-      const float* xo = xg + (int64_t)b0 * I;
-      float* yo = yg ? yg + (int64_t)b0 * O : nullptr;
-      const float* to = kLoss ? tg + (int64_t)b0 * O : nullptr;
-      if (one_bank)
-        sse += run_tile<1, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nobs, xo, yo, to, stg, lane);
-      else
-        sse += run_tile<2, kLoss>(pn, pe, out_pos, orow_first, n, I, O, nobs, xo, yo, to, stg, lane);
-    }
+    sse += run_unit<NB, kLoss>(rec, pe, nn, a.in_phase, pn, out_pos, orow_first, I, O, b0, a.B, xg,
+                               yg, tg, stg, lane);
   }
   return sse;
 }
@@ -360,76 +280,8 @@ __device__ __forceinline__ float reg_genome(TN_REG_PARAMS, int g, int t_begin, i
 // wavefronts of a workgroup mostly share a genome). With kLoss, one workgroup
 // per list entry whose wavefronts share its tiles and reduce the squared error
 // in a fixed order.
-template <int NB, bool kLoss>
-__global__ __launch_bounds__(kWave * 8) void forward_reg_kernel(TN_REG_PARAMS,
-                                                                float* __restrict__ loss) {
-  extern __shared__ __align__(16) float stage_all[];
-  __shared__ float part[8];
-  const int lane = lane_id();
-  const int wave = wave_id();
-  const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage;
-  int entry, t_begin, t_end, t_step;
-  if (kLoss) {
-    entry = blockIdx.x;
-    t_begin = wave;
-    t_end = a.n_tiles;
-    t_step = W;
-  } else {
-    const int64_t item = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * W + wave;
-    if (item >= a.n_items) return;  // wavefront-uniform; no barrier without kLoss
-    entry = (int)(item / a.n_groups);
-    t_begin = (int)(item - (int64_t)entry * a.n_groups) * a.per_wave;
-    t_end = min(t_begin + a.per_wave, a.n_tiles);
-    t_step = 1;
-  }
-  const int g = a.genomes ? a.genomes[entry] : entry;
-  int st;
-  const float sse = reg_genome<NB, kLoss>(TN_REG_ARGS, g, t_begin, t_end, t_step, stg, &st);
-  if (kLoss && st != -2) {  // st is uniform over the workgroup
-    // deterministic: fixed per-thread assignment, fixed reduction order
-    const float total = wave_sum(sse);
-    if (lane == 0) part[wave] = total;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float acc = 0.0f;
-      for (int v = 0; v < W; ++v) acc += part[v];
-      loss[g] = st ? __builtin_nanf("") : fmaf(a.scale, acc, a.offset);
-    }
-  }
-}
-
-// Persistent form: the workgroup takes the next W * chunk (list entry, unit)
-// items of its XCD's share from that share's counter (one atomic per grab) and
-// wavefront w runs items base + w, base + w + W, ...; list entries are ordered
-// longest first. The kXcds counters must be 0 at launch.
-template <int NB>
-__global__ __launch_bounds__(kWave * 8) void forward_reg_queue_kernel(TN_REG_PARAMS) {
-  extern __shared__ __align__(16) float stage_all[];
-  __shared__ int base_sh;
-  const int wave = wave_id();
-  const int W = blockDim.x / kWave;
-  float* stg = stage_all + wave * kStage;
-  const int x = blockIdx.x % kXcds;
-  const int n_share = share_items(a.n_list, x, a.n_tiles);
-  for (;;) {
-    if (threadIdx.x == 0) base_sh = atomicAdd(a.queue + x, W * a.per_wave);
-    __syncthreads();
-    const int base = __builtin_amdgcn_readfirstlane(base_sh);  // uniform: scalar program loads
-    __syncthreads();
-    if (base >= n_share) break;
-    for (int c = 0; c < a.per_wave; ++c) {
-      const int item = base + c * W + wave;
-      if (item >= n_share) break;
-      const int le = item / a.n_tiles, t = item - le * a.n_tiles;
-      int st;
-      reg_genome<NB, false>(TN_REG_ARGS, a.genomes[le * kXcds + x], t, t + 1, 1, stg, &st);
-    }
-  }
-}
-
-// The explicit-register-file forms of the two kernels above (R rows at
-// v[kRfBase ..]); the compiler gets the VGPRs below kRfBase.
+// The register file has R rows per tile at v[kRfBase ..]; the compiler gets
+// the VGPRs below kRfBase.
 template <int R, bool kLoss>
 __global__ __launch_bounds__(kWave * 8) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
 forward_rf_kernel(TN_REG_PARAMS, float* __restrict__ loss) {
@@ -469,6 +321,10 @@ forward_rf_kernel(TN_REG_PARAMS, float* __restrict__ loss) {
   }
 }
 
+// Persistent form: the workgroup takes the next W * chunk (list entry, unit)
+// items of its XCD's share from that share's counter (one atomic per grab) and
+// wavefront w runs items base + w, base + w + W, ...; list entries are ordered
+// longest first. The kXcds counters must be 0 at launch.
 template <int R>
 __global__ __launch_bounds__(kWave * 8) __attribute__((amdgpu_num_vgpr(TN_RF_BASE))) void
 forward_rf_queue_kernel(TN_REG_PARAMS) {
@@ -496,10 +352,9 @@ forward_rf_queue_kernel(TN_REG_PARAMS) {
   }
 }
 
-// Variants: 0 (one or two banks chosen per genome), 1 or 2 banks, or an
-// explicit register file of V rows per tile (50: four tiles per wavefront,
+// Variants: register files of V rows per tile (50: four tiles per wavefront,
 // 100: two, the others one).
-#define TN_REG_VARIANTS(X) X(0) X(1) X(2) X(32) X(50) X(64) X(96) X(100) X(128) X(160) X(200)
+#define TN_REG_VARIANTS(X) X(32) X(50) X(64) X(96) X(100) X(128) X(160) X(200)
 
 template <int V, bool kLoss>
 int launch_grid(const tn_population& p, const tn_transformed& t, const float* obs, float* out,
@@ -514,20 +369,14 @@ int launch_grid(const tn_population& p, const tn_transformed& t, const float* ob
                      reinterpret_cast<const int2*>(t.prog_edge), t.prog_rec, t.io_pos, obs, out, \
                      target, a,                                                              \
                      loss)
-  if constexpr (V >= 32)
-    TN_REG_LAUNCH((forward_rf_kernel<V, kLoss>));
-  else
-    TN_REG_LAUNCH((forward_reg_kernel<V, kLoss>));
+  TN_REG_LAUNCH((forward_rf_kernel<V, kLoss>));
 #undef TN_REG_LAUNCH
   return check_launch();
 }
 
 template <int V>
 const void* queue_kernel() {
-  if constexpr (V >= 32)
-    return (const void*)forward_rf_queue_kernel<V>;
-  else
-    return (const void*)forward_reg_queue_kernel<V>;
+  return (const void*)forward_rf_queue_kernel<V>;
 }
 
 template <int V>
@@ -543,10 +392,7 @@ int launch_queue(const tn_population& p, const tn_transformed& t, const float* o
                      reinterpret_cast<const int2*>(t.prog_edge), t.prog_rec, t.io_pos, obs,  \
                      out,                                                                    \
                      (const float*)nullptr, a)
-  if constexpr (V >= 32)
-    TN_REG_LAUNCH((forward_rf_queue_kernel<V>));
-  else
-    TN_REG_LAUNCH((forward_reg_queue_kernel<V>));
+  TN_REG_LAUNCH((forward_rf_queue_kernel<V>));
 #undef TN_REG_LAUNCH
   return check_launch();
 }
@@ -567,12 +413,9 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
                        int64_t obs_stride, int B, float* out, const RegTile& tile,
                        const FwdWork& work, hipStream_t stream) {
   const int waves = tile.waves <= 0 ? 4 : tile.waves;
-  const int rows = tile.rf ? tile.rf : (tile.rows <= 0 ? 64 : tile.rows);
-  const int variant = tile.rf ? tile.rf : tile.banks;
-  if (waves > 8 || !valid_variant(variant) ||
-      (!tile.rf && ((rows != 32 && rows != 64) || tile.banks < 0 || tile.banks > 2 ||
-                    (tile.banks == 1 && rows != 32))))
-    return TN_EINVAL;
+  const int rows = tile.rf;
+  const int variant = tile.rf;
+  if (waves > 8 || !valid_variant(variant)) return TN_EINVAL;
   const int n_list = work.genomes ? work.n_genomes : p.P;
   // units of stage_tiles(variant) tiles of 64 observations per genome
   const int kt = stage_tiles(variant);
@@ -610,16 +453,38 @@ int launch_forward_reg(const tn_population& p, const tn_transformed& t, const fl
   }
 }
 
+// The loss form of the register-file variant V: one workgroup of `waves`
+// wavefronts per genome (grid P), sharing its units; genomes outside
+// (rows_lo, V] are left to another launch when skip_above (else NaN above V).
+template <int V>
+int loss_rf(const tn_population& p, const tn_transformed& t, const float* obs,
+            int64_t obs_stride, int B, const float* target, int64_t target_stride, float scale,
+            float offset, float* out, float* loss, int waves, int rows_lo, bool skip_above,
+            hipStream_t stream) {
+  const int kt = stage_tiles(V);
+  const int n_units = ((B + kWave - 1) / kWave + kt - 1) / kt;
+  RegArgs a{obs_stride, B, target_stride, scale, offset, n_units, 1, n_units, V, rows_lo,
+            skip_above ? 1 : 0, nullptr, nullptr, 0, dma_phase(V, p.n_in),
+            stage_floats(V, p.n_in), p.P};
+  return launch_grid<V, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
+}
+
 int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, const float* obs,
                             int64_t obs_stride, int B, const float* target,
                             int64_t target_stride, float scale, float offset, float* out,
-                            float* loss, int waves, bool skip_above, hipStream_t stream) {
+                            float* loss, int waves, int rf, int rows_lo, bool skip_above,
+                            hipStream_t stream) {
   if (waves <= 0) waves = 4;
   if (waves > 8) return TN_EINVAL;
-  const int n_tiles = (B + kWave - 1) / kWave;
-  RegArgs a{obs_stride, B,  target_stride, scale,   offset, n_tiles, 1, n_tiles, 64, -1,
-            skip_above ? 1 : 0, nullptr, nullptr, 0, 0, stage_floats(0, p.n_in), p.P};
-  return launch_grid<0, true>(p, t, obs, out, target, loss, a, p.P, waves, stream);
+  switch (rf) {
+#define TN_CASE(V)                                                                           \
+  case V:                                                                                    \
+    return loss_rf<V>(p, t, obs, obs_stride, B, target, target_stride, scale, offset, out, loss, \
+                      waves, rows_lo, skip_above, stream);
+    TN_REG_VARIANTS(TN_CASE)
+#undef TN_CASE
+    default: return TN_EINVAL;
+  }
 }
 
 int reg_queue_grid(int variant, int waves, int n_in) {

@@ -18,13 +18,11 @@ struct FwdWork {
 // Register engine (forward_reg.hip).
 struct RegTile {
   int waves = 4;            // wavefronts per workgroup (1..8)
-  int rows = 64;            // 32 or 64 value rows in registers
-  int banks = 0;            // 1 or 2 register banks; 0: chosen per genome
-  int rf = 0;               // rows per tile of an explicit register file instead of
-                            // banks (32, 64, 96, 128, 160, 200: one tile of 64
-                            // observations per wavefront; 100: two; 50: four); 0: banks
+  int rf = 64;              // rows per tile of the register file (32, 64, 96, 128, 160,
+                            // 200: one tile of 64 observations per wavefront; 100: two;
+                            // 50: four)
   int rows_lo = -1;         // genomes with prog_rows <= rows_lo are skipped
-  bool skip_above = false;  // genomes with prog_rows > rows are skipped (else NaN)
+  bool skip_above = false;  // genomes with prog_rows > rf are skipped (else NaN)
 };
 
 // Level-parallel LDS engine (forward.hip).
@@ -58,12 +56,16 @@ constexpr int kRegRowsMax = 200;  // largest register file (rows per tile)
 int launch_forward_reg(const tn_population& p, const tn_transformed& t, const float* obs,
                        int64_t obs_stride, int B, float* out, const RegTile& tile,
                        const FwdWork& work, hipStream_t stream);
+// Forward pass with the squared-error epilogue on the register file of rf rows
+// (one workgroup per genome; genomes outside (rows_lo, rf] skipped when
+// skip_above).
 int launch_forward_loss_reg(const tn_population& p, const tn_transformed& t, const float* obs,
                             int64_t obs_stride, int B, const float* target,
                             int64_t target_stride, float scale, float offset, float* out,
-                            float* loss, int waves, bool skip_above, hipStream_t stream);
+                            float* loss, int waves, int rf, int rows_lo, bool skip_above,
+                            hipStream_t stream);
 // Resident workgroups (whole device) of the persistent register kernel of a
-// variant (0, 1, 2 banks or register-file rows).
+// register-file size.
 int reg_queue_grid(int variant, int waves, int n_in);
 
 int launch_forward(const tn_population& p, const tn_transformed& t, const float* obs,

@@ -1,22 +1,17 @@
 // Register-resident evaluation of a genome's packed program (the calculation
 // stage of TensorNEAT Section 3.3): one lane = one evaluation, node values in
-// registers addressed with a uniform index (s_set_gpr_idx), the program read
-// with scalar loads. Shared by the forward engine and the CPPN query of the
-// substrate. Two storage forms, chosen by the template parameter NB:
-//   NB = 1, 2   one or two 32-entry vector banks the compiler allocates (a
-//               row of the second bank costs a select);
-//   NB >= 32    an explicit register file of NB rows at v[kRfBase ..
-//               kRfBase + NB): the kernel limits the compiler to the VGPRs
-//               below kRfBase and reserves the file with a clobber, and every
-//               access is one s_set_gpr_idx window around one instruction (an
-//               in-edge is a single v_fmac_f32 with an indexed operand).
+// an explicit register file addressed with a uniform index (s_set_gpr_idx),
+// the program read across lanes. Shared by the forward engine and the CPPN
+// query of the substrate. The file of R rows per tile sits at v[kRfBase ..]:
+// the kernel limits the compiler to the VGPRs below kRfBase and reserves the
+// file with a clobber, and every access is one s_set_gpr_idx window around
+// one instruction per tile (an in-edge is a single v_fmac_f32 with an indexed
+// operand).
 #pragma once
 
 #include "fwd_core.hpp"
 
 namespace tn {
-
-typedef float f32x32 __attribute__((ext_vector_type(32)));
 
 // First VGPR of the explicit register file; kernels using it carry
 // __attribute__((amdgpu_num_vgpr(kRfBase))).
@@ -138,124 +133,9 @@ __device__ __forceinline__ void rfk_get(int r, float (&x)[rf_tiles(R)]) {
   }
 }
 
-// Node values of one lane: rows 0..31 in bank lo, rows 32..63 in bank hi
-// (NB = 2). The banks are plain local vectors (a struct around them makes the
-// compiler keep them in scratch memory).
-template <int NB>
-__device__ __forceinline__ float vget(const f32x32& lo, const f32x32& hi, int r) {
-  if constexpr (NB >= 32) return rf_get(r);
-  if (NB == 1) return lo[r];
-  const int r0 = r & 31;
-  const float a = lo[r0], b = hi[r0];
-  return r < 32 ? a : b;
-}
-
-// Both banks are written at r & 31, the untouched one with its own value: a
-// write under a branch would make the compiler copy the whole bank.
-template <int NB>
-__device__ __forceinline__ void vset(f32x32& lo, f32x32& hi, int r, float x) {
-  if constexpr (NB >= 32) {
-    rf_set(r, x);
-    return;
-  }
-  if (NB == 1) {
-    lo[r] = x;
-    return;
-  }
-  const int r0 = r & 31;
-  const float o0 = lo[r0], o1 = hi[r0];
-  lo[r0] = r < 32 ? x : o0;
-  hi[r0] = r < 32 ? o1 : x;
-}
-
 // Program row of (non-input) position p: bits 16..30 of its function word.
 __device__ __forceinline__ int prog_row(const int4* __restrict__ pn, int p) {
   return (pn[p].y >> 16) & 0x7fff;
-}
-
-// s += w * value of the edge's source row (one in-edge of the sum).
-template <int NB>
-__device__ __forceinline__ void edge_fma(const f32x32& lo, const f32x32& hi, float& s, int2 q) {
-  if constexpr (NB >= 32)
-    rf_fma(s, __int_as_float(q.y), q.x);
-  else
-    s = fmaf(__int_as_float(q.y), vget<NB>(lo, hi, q.x), s);
-}
-
-// In-edges e .. e1-1 of one position, aggregated (Section 3.3's f_agg); g
-// holds the first 8 edge words from e on (loaded ahead). Edge words may be
-// read up to 7 past e1 (tn_transformed.prog_edge is padded for that).
-template <int NB>
-__device__ __forceinline__ float aggregate(const f32x32& lo, const f32x32& hi,
-                                           const int2* __restrict__ pe, const int2 (&g)[8],
-                                           int e, int e1, int agg) {
-  const int cnt = e1 - e;
-  float s = 0.0f;
-  if (agg == TN_AGG_SUM) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (u < cnt) edge_fma<NB>(lo, hi, s, g[u]);
-    // further edges 8 at a time (one s_load_dwordx16; scalar loads return out
-    // of order, so each use waits for all of them)
-    for (int b = e + 8; b < e1; b += 8) {
-      int2 q[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) q[u] = pe[b + u];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b + u < e1) edge_fma<NB>(lo, hi, s, q[u]);
-    }
-    return s;
-  }
-  if (cnt == 0) return s;
-  s = __int_as_float(g[0].y) * vget<NB>(lo, hi, g[0].x);
-  for (int i = e + 1; i < e1; ++i) {
-    const int2 q = pe[i];
-    const float t = __int_as_float(q.y) * vget<NB>(lo, hi, q.x);
-    switch (agg) {
-      case TN_AGG_PRODUCT: s = s * t; break;
-      case TN_AGG_MAX: s = fmaxf(s, t); break;
-      case TN_AGG_MIN: s = fminf(s, t); break;
-      case TN_AGG_MEAN: s = s + t; break;
-      default: s = fabsf(t) > fabsf(s) ? t : s; break;  // maxabs
-    }
-  }
-  if (agg == TN_AGG_MEAN) s = s / (float)cnt;
-  return s;
-}
-
-// The program of one genome, in topological order, on this lane's registers;
-// input rows must already hold the inputs. Software-pipelined over positions:
-// position p's in-edges are consumed first, then the header and first edge
-// group of position p+1 are requested, and p's activation runs while those
-// scalar loads are in flight.
-template <int NB>
-__device__ __forceinline__ void walk_program(f32x32& lo, f32x32& hi, const int4* __restrict__ pn,
-                                             const int2* __restrict__ pe, int n) {
-  int e = 0;
-  int4 h = pn[0];
-  int2 g[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) g[u] = pe[u];
-  for (int p = 0; p < n; ++p) {
-    const int f = h.y, e1 = h.x;
-    float s = 0.0f;
-    if (f >= 0) s = aggregate<NB>(lo, hi, pe, g, e, e1, (f >> 8) & 0xff);
-    const int4 nh = pn[p + 1 < n ? p + 1 : p];
-    int2 ng[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ng[u] = pe[e1 + u];
-    if (f >= 0) {  // an input's row already holds its value
-      const float z[1] = {fmaf(__int_as_float(h.w), s, __int_as_float(h.z))};
-      float a[1];
-      activate_all<1>(f & 0xff, z, a);
-      vset<NB>(lo, hi, (f >> 16) & 0x7fff, a[0]);
-    }
-    e = e1;
-    h = nh;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) g[u] = ng[u];
-  }
 }
 
 // One non-input position of the register-file walk, on every tile of the
