@@ -219,6 +219,23 @@ __device__ __forceinline__ const float* src_row(const float* mine, const EdgeRec
     return mine + q.src * kRow;
 }
 
+// s[k] += w * x[k] over in-edges e .. e+N-1 in ascending order, the N records
+// requested first, then the N source values.
+template <int N, int K, int kRow, class Prog>
+__device__ __forceinline__ void sum_edges(const Prog& prog, int e, const float* mine, float (&s)[K]) {
+  EdgeRec q[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) q[j] = prog.edge(e + j);
+  Vec<K> x[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) x[j].load(src_row<kRow, Prog>(mine, q[j]));
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = fmaf(q[j].w, x[j].x[k], s[k]);
+  }
+}
+
 template <int K, int kRow, class Prog>
 __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) {
   const NodeRec rec = prog.node(p);
@@ -232,28 +249,14 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = 0.0f;
     int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const EdgeRec q0 = prog.edge(e), q1 = prog.edge(e + 1), q2 = prog.edge(e + 2),
-                    q3 = prog.edge(e + 3);
-      Vec<K> x0, x1, x2, x3;
-      x0.load(src_row<kRow, Prog>(mine, q0));
-      x1.load(src_row<kRow, Prog>(mine, q1));
-      x2.load(src_row<kRow, Prog>(mine, q2));
-      x3.load(src_row<kRow, Prog>(mine, q3));
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        s[k] = fmaf(q0.w, x0.x[k], s[k]);
-        s[k] = fmaf(q1.w, x1.x[k], s[k]);
-        s[k] = fmaf(q2.w, x2.x[k], s[k]);
-        s[k] = fmaf(q3.w, x3.x[k], s[k]);
-      }
-    }
-    for (; e < e1; ++e) {
-      const EdgeRec q = prog.edge(e);
-      Vec<K> x;
-      x.load(src_row<kRow, Prog>(mine, q));
-#pragma unroll
-      for (int k = 0; k < K; ++k) s[k] = fmaf(q.w, x.x[k], s[k]);
+    for (; e + 4 <= e1; e += 4) sum_edges<4, K, kRow>(prog, e, mine, s);
+    // the last one to three in-edges unrolled: their records requested
+    // together, then their source values
+    switch (e1 - e) {
+      case 1: sum_edges<1, K, kRow>(prog, e, mine, s); break;
+      case 2: sum_edges<2, K, kRow>(prog, e, mine, s); break;
+      case 3: sum_edges<3, K, kRow>(prog, e, mine, s); break;
+      default: break;
     }
   } else if (e0 == e1) {
 #pragma unroll
