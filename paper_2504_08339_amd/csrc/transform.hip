@@ -2,13 +2,16 @@
 // per genome, the topological order N_order and the expanded connections
 // C_exp, the latter kept as a compressed in-edge list per topological position.
 //
-// One wavefront (64 lanes) per genome; everything for the genome lives in LDS:
+// One workgroup of 1..8 wavefronts per genome (more for populations of larger
+// genomes: every loop over node rows, connection rows, positions and edges is
+// split over the workgroup's threads); everything for the genome lives in LDS:
 //   1. node keys -> rows through an open-addressing hash (duplicate keys flagged)
 //   2. connection markings (in-key, out-key) through a 64-bit hash (duplicates
 //      flagged), enabled rows resolved to (source row, destination row)
-//   3. level-synchronous Kahn sort: each round takes a ballot over the node
-//      rows whose remaining in-degree is 0, places them by mbcnt in ascending
-//      row order, then decrements their successors through an out-edge list
+//   3. level-synchronous Kahn sort: each round marks the node rows whose
+//      remaining in-degree is 0, places them in ascending row order (a prefix
+//      sum over the workgroup), then decrements their successors through an
+//      out-edge list
 //   4. in-edge lists grouped by destination position: rows are dropped into
 //      buckets with LDS atomics, then each edge computes its rank among the
 //      bucket's rows, which makes the result independent of atomic order.
@@ -48,7 +51,7 @@ struct Layout {
   int HN, HC;              // hash table sizes (powers of two)
   int off_hkey, off_hslot, off_nkey, off_deg, off_rem, off_outdeg, off_pos,
       off_order, off_level, off_ptr, off_cursor, off_outlist, off_esrc, off_edst,
-      off_tmp, off_chash, off_csr_row;
+      off_tmp, off_chash, off_csr_row, off_lstart;
   size_t bytes;
 };
 
@@ -86,6 +89,7 @@ Layout make_layout(int N, int C) {
   L.off_edst = take(sizeof(int16_t) * C);
   L.off_tmp = take(sizeof(int16_t) * C);
   L.off_csr_row = take(sizeof(int16_t) * C);
+  L.off_lstart = take(sizeof(int16_t) * (N + 1));
   L.bytes = o;
   return L;
 }
@@ -104,9 +108,9 @@ __device__ int lookup_node(const int32_t* hkey, const int16_t* hslot, int HN, in
 // Writes the "no valid transformation" form of genome g.
 __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int st,
                               int64_t nb, int64_t nrows, int64_t cb, int64_t crows) {
-  const int lane = lane_id();
+  const int lane = threadIdx.x, T = blockDim.x;
   const int64_t rb = pop.rowptr_base(g);
-  for (int64_t p = lane; p < nrows; p += kWave) {
+  for (int64_t p = lane; p < nrows; p += T) {
     tr.order[nb + p] = -1;
     tr.level[nb + p] = -1;
     tr.pos_bias[nb + p] = 0.0f;
@@ -116,15 +120,15 @@ __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int s
     tr.prog_node[nb + p] = make_int4(0, 0, 0, 0);
     for (int j = 0; j < 4; ++j) reinterpret_cast<int4*>(tr.prog_rec)[(nb + p) * 4 + j] = make_int4(0, 0, 0, 0);
   }
-  for (int64_t p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = 0;
-  for (int64_t e = lane; e < crows; e += kWave) {
+  for (int64_t p = lane; p <= nrows; p += T) tr.row_ptr[rb + p] = 0;
+  for (int64_t e = lane; e < crows; e += T) {
     tr.edge_src[cb + e] = -1;
     tr.edge_row[cb + e] = -1;
     tr.edge_w[cb + e] = 0.0f;
     tr.prog_edge[cb + e] = make_int2(0, 0);
   }
   const int nio = pop.n_in + pop.n_out;
-  for (int k = lane; k < nio; k += kWave) tr.io_pos[(int64_t)g * nio + k] = -1;
+  for (int k = lane; k < nio; k += T) tr.io_pos[(int64_t)g * nio + k] = -1;
   if (lane == 0) {
     tr.status[g] = st;
     tr.n_valid[g] = 0;
@@ -133,12 +137,113 @@ __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int s
   }
 }
 
-__global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr, Layout L) {
+constexpr int kTfMaxWaves = 8;
+
+// Workgroup barrier that orders LDS accesses only: the kernel never reads back
+// what it stores to global memory, so its stores stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Workgroup-wide steps of the transform for workgroups of up to kW
+// wavefronts, over the threads in index order; with kW == 1 everything stays
+// inside the wavefront (no workgroup barrier). The multi-wavefront forms wait
+// at barriers: every thread of the workgroup calls them.
+template <int kW>
+struct Group {
+  int* sh;  // kW ints of LDS
+
+  __device__ __forceinline__ void sync() const {
+    if constexpr (kW == 1)
+      wave_sync();
+    else
+      lds_barrier();
+  }
+
+  // Sum of x over the earlier threads; *total: over the workgroup.
+  __device__ __forceinline__ int excl_sum(int x, int* total) const {
+    const int inc = wave_inclusive_scan(x);
+    if constexpr (kW == 1) {
+      *total = __shfl(inc, kWave - 1, kWave);
+      return inc - x;
+    } else {
+      const int lane = lane_id(), wave = (int)(threadIdx.x / kWave), W = (int)(blockDim.x / kWave);
+      if (lane == kWave - 1) sh[wave] = inc;
+      lds_barrier();
+      int before = 0, tot = 0;
+      for (int w = 0; w < W; ++w) {
+        const int t = sh[w];
+        before += w < wave ? t : 0;
+        tot += t;
+      }
+      lds_barrier();
+      *total = tot;
+      return before + inc - x;
+    }
+  }
+
+  // Number of earlier threads with f set; *total: over the workgroup.
+  __device__ __forceinline__ int excl_count(bool f, int* total) const {
+    const uint64_t m = __ballot(f);
+    if constexpr (kW == 1) {
+      *total = __popcll(m);
+      return mbcnt(m);
+    } else {
+      const int lane = lane_id(), wave = (int)(threadIdx.x / kWave), W = (int)(blockDim.x / kWave);
+      if (lane == 0) sh[wave] = __popcll(m);
+      lds_barrier();
+      int before = 0, tot = 0;
+      for (int w = 0; w < W; ++w) {
+        const int t = sh[w];
+        before += w < wave ? t : 0;
+        tot += t;
+      }
+      lds_barrier();
+      *total = tot;
+      return before + mbcnt(m);
+    }
+  }
+
+  // max(carry, x of this and every earlier thread); *prev: the same at the
+  // previous thread (carry at thread 0), *all: at the last thread.
+  __device__ __forceinline__ int incl_max(int x, int carry, int* prev, int* all) const {
+    const int lane = lane_id();
+    int before = carry, tot;
+    const int inc = wave_inclusive_max(x);
+    if constexpr (kW == 1) {
+      tot = max(carry, __shfl(inc, kWave - 1, kWave));
+    } else {
+      const int wave = (int)(threadIdx.x / kWave), W = (int)(blockDim.x / kWave);
+      if (lane == kWave - 1) sh[wave] = inc;
+      lds_barrier();
+      tot = carry;
+      for (int w = 0; w < W; ++w) {
+        const int t = sh[w];
+        if (w < wave) before = max(before, t);
+        tot = max(tot, t);
+      }
+      lds_barrier();
+    }
+    const int v = max(before, inc);
+    int pv = __shfl_up(v, 1, kWave);
+    if (lane == 0) pv = before;
+    *prev = pv;
+    *all = tot;
+    return v;
+  }
+};
+
+template <int kW>
+__global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrView tr, Layout L) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int flags;
+  __shared__ int scan_sh[kW];
+  const Group<kW> G{scan_sh};
 
   const int g = blockIdx.x;
-  const int lane = lane_id();
+  const int tid = threadIdx.x, T = blockDim.x;
   const int N = pop.N_max, C = pop.C_max;
 
   const int64_t nb = pop.node_base(g);
@@ -170,21 +275,22 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   int16_t* tmp = (int16_t*)(smem + L.off_tmp);
   int16_t* csr_row = (int16_t*)(smem + L.off_csr_row);  // connection row of CSR entry e
   int16_t* csr_src = outlist;                              // source position of entry e
+  int16_t* lstart = (int16_t*)(smem + L.off_lstart);    // first position of each level
 
-  for (int i = lane; i < L.HN; i += kWave) hkey[i] = kEmptyKey;
-  for (int i = lane; i < L.HC; i += kWave) chash[i] = kEmptyMark;
-  for (int i = lane; i < nrows; i += kWave) {
+  for (int i = tid; i < L.HN; i += T) hkey[i] = kEmptyKey;
+  for (int i = tid; i < L.HC; i += T) chash[i] = kEmptyMark;
+  for (int i = tid; i < nrows; i += T) {
     deg[i] = 0;
     outdeg[i] = 0;
     cursor[i] = 0;
     pos_of[i] = -1;
   }
-  if (lane == 0) flags = 0;
-  __syncthreads();
+  if (tid == 0) flags = 0;
+  G.sync();
 
   // 1. node rows -> hash
   int my_valid = 0;
-  for (int r = lane; r < nrows; r += kWave) {
+  for (int r = tid; r < nrows; r += T) {
     const int32_t k = pop.node_key[nb + r];
     nkey[r] = k;
     if (k < 0) continue;
@@ -205,16 +311,17 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
       h = (h + 1) & (uint32_t)(L.HN - 1);
     }
   }
-  const int n_valid = wave_sum_int(my_valid);
-  __syncthreads();
+  int n_valid;
+  (void)G.excl_sum(my_valid, &n_valid);
+  G.sync();
 
   // 2. inputs / outputs present
   const int nio = pop.n_in + pop.n_out;
-  for (int k = lane; k < nio; k += kWave)
+  for (int k = tid; k < nio; k += T)
     if (lookup_node(hkey, hslot, L.HN, k) < 0) atomicOr(&flags, TN_MISSING_IO);
 
   // 3. connection rows
-  for (int r = lane; r < crows; r += kWave) {
+  for (int r = tid; r < crows; r += T) {
     const int32_t a = pop.conn_in[cb + r];
     const int32_t b = pop.conn_out[cb + r];
     int16_t s = -1, d = -1;
@@ -246,7 +353,7 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
     esrc[r] = s;
     edst[r] = d;
   }
-  __syncthreads();
+  G.sync();
   const int st = flags;
   if (st) {
     write_flagged(pop, tr, g, st, nb, nrows, cb, crows);
@@ -256,48 +363,51 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   // 4. out-edge lists by source row
   {
     int carry = 0;
-    for (int base = 0; base < nrows; base += kWave) {
-      const int i = base + lane;
+    for (int base = 0; base < nrows; base += T) {
+      const int i = base + tid;
       const int x = i < nrows ? outdeg[i] : 0;
-      const int inc = wave_inclusive_scan(x);
+      int tot;
+      const int ex = G.excl_sum(x, &tot);
       if (i < nrows) {
-        ptr[i] = carry + inc - x;
+        ptr[i] = carry + ex;
         rem[i] = deg[i];
       }
-      carry += __shfl(inc, kWave - 1, kWave);
+      carry += tot;
     }
-    if (lane == 0) ptr[nrows] = carry;
+    if (tid == 0) ptr[nrows] = carry;
   }
-  __syncthreads();
-  for (int r = lane; r < crows; r += kWave) {
+  G.sync();
+  for (int r = tid; r < crows; r += T) {
     const int s = esrc[r];
     if (s >= 0) outlist[ptr[s] + atomicAdd(&cursor[s], 1)] = edst[r];
   }
-  __syncthreads();
+  G.sync();
 
-  // 5. level-synchronous Kahn rounds
+  // 5. level-synchronous Kahn rounds; a round's rows are placed in ascending
+  // row order
   int emitted = 0;
   for (int lvl = 0;; ++lvl) {
     const int start = emitted;
-    for (int base = 0; base < nrows; base += kWave) {
-      const int i = base + lane;
+    for (int base = 0; base < nrows; base += T) {
+      const int i = base + tid;
       const bool ready = i < nrows && nkey[i] >= 0 && pos_of[i] < 0 && rem[i] == 0;
-      const uint64_t m = __ballot(ready);
+      int cnt;
+      const int ex = G.excl_count(ready, &cnt);
       if (ready) {
-        const int p = emitted + mbcnt(m);
+        const int p = emitted + ex;
         pos_of[i] = (int16_t)p;
         order_l[p] = (int16_t)i;
         level_l[p] = (int16_t)lvl;
       }
-      emitted += __popcll(m);
+      emitted += cnt;
     }
     if (emitted == start) break;
-    __syncthreads();
-    for (int p = start + lane; p < emitted; p += kWave) {
+    G.sync();
+    for (int p = start + tid; p < emitted; p += T) {
       const int s = order_l[p];
       for (int j = ptr[s]; j < ptr[s + 1]; ++j) atomicSub(&rem[outlist[j]], 1);
     }
-    __syncthreads();
+    G.sync();
   }
   if (emitted < n_valid) {
     write_flagged(pop, tr, g, TN_CYCLE, nb, nrows, cb, crows);
@@ -305,29 +415,30 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   }
 
   // 6. in-edge row pointers over topological positions
-  __syncthreads();
+  G.sync();
   {
     int carry = 0;
-    for (int base = 0; base < n_valid; base += kWave) {
-      const int p = base + lane;
+    for (int base = 0; base < n_valid; base += T) {
+      const int p = base + tid;
       const int x = p < n_valid ? deg[order_l[p]] : 0;
-      const int inc = wave_inclusive_scan(x);
-      if (p < n_valid) ptr[p] = carry + inc - x;
-      carry += __shfl(inc, kWave - 1, kWave);
+      int tot;
+      const int ex = G.excl_sum(x, &tot);
+      if (p < n_valid) ptr[p] = carry + ex;
+      carry += tot;
     }
-    if (lane == 0) ptr[n_valid] = carry;
-    for (int i = lane; i < nrows; i += kWave) cursor[i] = 0;
+    if (tid == 0) ptr[n_valid] = carry;
+    for (int i = tid; i < nrows; i += T) cursor[i] = 0;
   }
-  __syncthreads();
+  G.sync();
   const int n_edges = ptr[n_valid];
-  for (int r = lane; r < crows; r += kWave) {
+  for (int r = tid; r < crows; r += T) {
     const int d = edst[r];
     if (d >= 0) tmp[ptr[pos_of[d]] + atomicAdd(&cursor[d], 1)] = (int16_t)r;
   }
-  __syncthreads();
+  G.sync();
 
   // 7. stable order inside each bucket, written out
-  for (int idx = lane; idx < n_edges; idx += kWave) {
+  for (int idx = tid; idx < n_edges; idx += T) {
     const int r = tmp[idx];
     const int pd = pos_of[edst[r]];
     const int lo = ptr[pd], hi = ptr[pd + 1];
@@ -340,16 +451,17 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
     csr_row[lo + rank] = (int16_t)r;
     csr_src[lo + rank] = pos_of[esrc[r]];
   }
-  for (int e = n_edges + lane; e < crows; e += kWave) {
+  for (int e = n_edges + tid; e < crows; e += T) {
     tr.edge_row[cb + e] = -1;
     tr.edge_src[cb + e] = -1;
     tr.edge_w[cb + e] = 0.0f;
   }
   const int64_t rb = pop.rowptr_base(g);
-  for (int p = lane; p <= nrows; p += kWave) tr.row_ptr[rb + p] = ptr[p < n_valid ? p : n_valid];
+  for (int p = tid; p <= nrows; p += T) tr.row_ptr[rb + p] = ptr[p < n_valid ? p : n_valid];
 
-  // 8. node attributes by position
-  for (int p = lane; p < nrows; p += kWave) {
+  // 8. node attributes by position; level starts (the start of level L is the
+  // one position of level L whose predecessor has a lower level)
+  for (int p = tid; p < nrows; p += T) {
     if (p < n_valid) {
       const int s = order_l[p];
       tr.order[nb + p] = s;
@@ -360,6 +472,7 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
       uint32_t fn = (uint32_t)pop.node_act[nb + s] | ((uint32_t)pop.node_agg[nb + s] << 8);
       if (k < pop.n_in) fn = kFnInput | ((uint32_t)k << 16) | fn;
       tr.pos_fn[nb + p] = (int32_t)fn;
+      if (p == 0 || level_l[p - 1] != level_l[p]) lstart[level_l[p]] = (int16_t)p;
     } else {
       tr.order[nb + p] = -1;
       tr.level[nb + p] = -1;
@@ -368,7 +481,9 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
       tr.pos_fn[nb + p] = 0;
     }
   }
-  for (int k = lane; k < nio; k += kWave)
+  const int n_levels = n_valid > 0 ? level_l[n_valid - 1] + 1 : 0;
+  if (tid == 0) lstart[n_levels] = (int16_t)n_valid;
+  for (int k = tid; k < nio; k += T)
     tr.io_pos[(int64_t)g * nio + k] = pos_of[lookup_node(hkey, hslot, L.HN, k)];
 
   // 9. value rows with reuse (see the header). last[s]: position of the last
@@ -377,37 +492,35 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   __shared__ int next_row;
   int32_t* last = deg;  // both are free now
   int32_t* row = rem;
-  for (int p = lane; p < n_valid; p += kWave) last[p] = -1;
-  for (int w = lane; w < TN_MAX_NODES / 32; w += kWave) free_bits[w] = 0u;
-  wave_sync();
-  for (int p = lane; p < n_valid; p += kWave)
+  for (int p = tid; p < n_valid; p += T) last[p] = -1;
+  for (int w = tid; w < TN_MAX_NODES / 32; w += T) free_bits[w] = 0u;
+  G.sync();
+  for (int p = tid; p < n_valid; p += T)
     for (int j = ptr[p]; j < ptr[p + 1]; ++j) atomicMax(&last[csr_src[j]], p);
-  wave_sync();
+  G.sync();
   // input k takes row k; an input nobody reads is free at once
-  for (int p = lane; p < n_valid; p += kWave) {
+  for (int p = tid; p < n_valid; p += T) {
     const int k = nkey[order_l[p]];
     if (k < pop.n_in) {
       row[p] = k;
       if (last[p] < 0) atomicOr(&free_bits[k >> 5], 1u << (k & 31));
     }
   }
-  if (lane == 0) next_row = pop.n_in;
-  wave_sync();
-  for (int lb = 0; lb < n_valid;) {
-    const int lvl_here = level_l[lb];
-    int le = lb + 1;
-    while (le < n_valid && level_l[le] == lvl_here) ++le;  // uniform scan
-    // allocate the level's non-input positions, in order
-    for (int base = lb; base < le; base += kWave) {
-      const int p = base + lane;
+  if (tid == 0) next_row = pop.n_in;
+  G.sync();
+  for (int l = 0; l < n_levels; ++l) {
+    const int lb = lstart[l], le = lstart[l + 1];
+    // allocate the level's non-input positions, in order: the i-th takes the
+    // i-th lowest free row, or a new one once the free rows are used up
+    for (int base = lb; base < le; base += T) {
+      const int p = base + tid;
       const bool node = p < le && nkey[order_l[p]] >= pop.n_in;
-      const uint64_t m = __ballot(node);
-      const int k = __popcll(m);
+      int k;
+      const int i = G.excl_count(node, &k);
       if (k == 0) continue;
-      const int i = mbcnt(m);
-      // free rows available
       int nfree = 0;
       for (int w = 0; w < TN_MAX_NODES / 32; ++w) nfree += __popc(free_bits[w]);
+      const int nr = next_row;
       if (node) {
         int r;
         if (i < nfree) {
@@ -417,29 +530,28 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
           for (int t = 0; t < skip; ++t) x &= x - 1;
           r = w * 32 + (__ffs(x) - 1);
         } else {
-          r = next_row + (i - nfree);
+          r = nr + (i - nfree);
         }
         row[p] = r;
       }
-      wave_sync();
+      G.sync();
       if (node && i < nfree) atomicAnd(&free_bits[row[p] >> 5], ~(1u << (row[p] & 31)));
-      if (lane == 0 && k > nfree) next_row += k - nfree;
-      wave_sync();
+      if (tid == 0 && k > nfree) next_row = nr + (k - nfree);
+      G.sync();
     }
     // free the rows whose last consumer sits in this level, and those of this
     // level's positions that nothing reads
-    for (int q = lane; q < n_valid; q += kWave) {
+    for (int q = tid; q < n_valid; q += T) {
       const int key = nkey[order_l[q]];
       const bool is_out = key >= pop.n_in && key < pop.n_in + pop.n_out;
       const bool dead_here = last[q] < 0 && key >= pop.n_in && q >= lb && q < le;
       if (!is_out && ((last[q] >= lb && last[q] < le) || dead_here))
         atomicOr(&free_bits[row[q] >> 5], 1u << (row[q] & 31));
     }
-    wave_sync();
-    lb = le;
+    G.sync();
   }
-  for (int p = lane; p < nrows; p += kWave) tr.pos_row[nb + p] = p < n_valid ? row[p] : -1;
-  wave_sync();
+  for (int p = tid; p < nrows; p += T) tr.pos_row[nb + p] = p < n_valid ? row[p] : -1;
+  G.sync();
 
   // 9b. value rows of the packed program, which is evaluated one position
   // after the other: a value's row is free as soon as its last consumer has
@@ -459,17 +571,18 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   int32_t* seq = cursor;                         // row, or -(s+1): the row of position s
   int16_t* ev = (int16_t*)(smem + L.off_chash);  // position whose row the u-th event frees
   int n_unused = 0;
-  for (int base = 0; base < n_valid; base += kWave) {
-    const int p = base + lane;
+  for (int base = 0; base < n_valid; base += T) {
+    const int p = base + tid;
     const bool un = p < n_valid && nkey[order_l[p]] < pop.n_in && last[p] < 0;
-    const uint64_t m = __ballot(un);
-    if (un) ev[n_unused + mbcnt(m)] = (int16_t)p;
-    n_unused += __popcll(m);
+    int cnt;
+    const int ex = G.excl_count(un, &cnt);
+    if (un) ev[n_unused + ex] = (int16_t)p;
+    n_unused += cnt;
   }
   {
     int carry = n_unused;
-    for (int base = 0; base < n_valid; base += kWave) {
-      const int p = base + lane;
+    for (int base = 0; base < n_valid; base += T) {
+      const int p = base + tid;
       int c = 0;
       if (p < n_valid) {
         if (p > 0) c += nkey[order_l[p - 1]] >= nio && last[p - 1] < 0;
@@ -479,13 +592,14 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
           c += last[s] == p && !(ks >= pop.n_in && ks < nio);
         }
       }
-      const int incl = wave_inclusive_scan(c);
-      if (p < n_valid) fcum[p] = carry + incl;
-      carry += __shfl(incl, kWave - 1, kWave);
+      int tot;
+      const int ex = G.excl_sum(c, &tot);
+      if (p < n_valid) fcum[p] = carry + ex + c;
+      carry += tot;
     }
   }
-  wave_sync();
-  for (int p = 1 + lane; p < n_valid; p += kWave) {
+  G.sync();
+  for (int p = 1 + tid; p < n_valid; p += T) {
     int i = fcum[p - 1];
     if (nkey[order_l[p - 1]] >= nio && last[p - 1] < 0) ev[i++] = (int16_t)(p - 1);
     for (int j = ptr[p]; j < ptr[p + 1]; ++j) {
@@ -494,19 +608,19 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
       if (last[s] == p && !(ks >= pop.n_in && ks < nio)) ev[i++] = (int16_t)s;
     }
   }
-  wave_sync();
+  G.sync();
   int n_new = 0;  // rows created so far (beyond the n_in input rows)
   {
     int a_carry = 0;
-    for (int base = 0; base < n_valid; base += kWave) {
-      const int p = base + lane;
+    for (int base = 0; base < n_valid; base += T) {
+      const int p = base + tid;
       const int k = p < n_valid ? nkey[order_l[p]] : 0;
       const bool node = p < n_valid && k >= pop.n_in;
-      const int a = a_carry + wave_inclusive_scan(node ? 1 : 0);
+      int a_tot;
+      const int a = a_carry + G.excl_count(node, &a_tot) + (node ? 1 : 0);
       const int d = node ? a - fcum[p] : INT_MIN;
-      const int nn = max(n_new, wave_inclusive_max(d));
-      int prev = __shfl_up(nn, 1, kWave);
-      if (lane == 0) prev = n_new;
+      int prev, all;
+      const int nn = G.incl_max(d, n_new, &prev, &all);
       if (p < n_valid) {
         if (!node)
           seq[p] = k;
@@ -515,15 +629,17 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
         else
           seq[p] = -(ev[a - nn - 1] + 1);
       }
-      a_carry = __shfl(a, kWave - 1, kWave);
-      n_new = __shfl(nn, kWave - 1, kWave);
+      a_carry += a_tot;
+      n_new = all;
     }
   }
-  wave_sync();
-  // resolve "same row as position s" links by pointer jumping (s < p always)
+  G.sync();
+  // resolve "same row as position s" links by pointer jumping (s < p always;
+  // a link read while another thread replaces it is either value, both on the
+  // same chain, so the rounds end with every position holding its chain's row)
   for (;;) {
     bool more = false;
-    for (int p = lane; p < n_valid; p += kWave) {
+    for (int p = tid; p < n_valid; p += T) {
       const int v = seq[p];
       if (v < 0) {
         const int t = seq[-v - 1];
@@ -531,12 +647,14 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
         more |= t < 0;
       }
     }
-    wave_sync();
-    if (__ballot(more) == 0) break;
+    G.sync();
+    int n_more;
+    (void)G.excl_count(more, &n_more);
+    if (n_more == 0) break;
   }
 
   // 10. packed program of the forward pass
-  for (int p = lane; p < nrows; p += kWave) {
+  for (int p = tid; p < nrows; p += T) {
     int4 q = make_int4(0, 0, 0, 0);
     if (p < n_valid) {
       const int s = order_l[p];
@@ -548,7 +666,7 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
     }
     tr.prog_node[nb + p] = q;
   }
-  for (int e = lane; e < crows; e += kWave) {
+  for (int e = tid; e < crows; e += T) {
     int2 q = make_int2(0, 0);
     if (e < n_edges) q = make_int2(seq[csr_src[e]], __float_as_int(pop.conn_w[cb + csr_row[e]]));
     tr.prog_edge[cb + e] = q;
@@ -563,13 +681,14 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
   {
     const int zrow = pop.n_in + n_new;
     int in_before = 0;
-    for (int base = 0; base < n_valid; base += kWave) {
-      const int p = base + lane;
+    for (int base = 0; base < n_valid; base += T) {
+      const int p = base + tid;
       const bool inp = p < n_valid && nkey[order_l[p]] < pop.n_in;
-      const uint64_t m = __ballot(inp);
+      int cnt;
+      const int ex = G.excl_count(inp, &cnt);
       if (p < n_valid && !inp) {
         const int s = order_l[p];
-        const int r = p - (in_before + mbcnt(m));
+        const int r = p - (in_before + ex);
         const int e0 = ptr[p], ne = ptr[p + 1] - e0;
         int32_t w[16];
         w[0] = (int32_t)((uint32_t)pop.node_act[nb + s] | ((uint32_t)pop.node_agg[nb + s] << 3) |
@@ -589,13 +708,13 @@ __global__ __launch_bounds__(kWave) void transform_kernel(PopView pop, TrView tr
         rec[2] = make_int4(w[8], w[9], w[10], w[11]);
         rec[3] = make_int4(w[12], w[13], w[14], w[15]);
       }
-      in_before += __popcll(m);
+      in_before += cnt;
     }
     const int n_nodes = n_valid - in_before;
-    for (int i = n_nodes * 4 + lane; i < nrows * 4; i += kWave)
+    for (int i = n_nodes * 4 + tid; i < nrows * 4; i += T)
       reinterpret_cast<int4*>(tr.prog_rec)[nb * 4 + i] = make_int4(0, 0, 0, 0);
   }
-  if (lane == 0) {
+  if (tid == 0) {
     tr.status[g] = 0;
     tr.n_valid[g] = n_valid;
     tr.n_rows[g] = next_row;
@@ -609,10 +728,21 @@ size_t transform_lds_bytes(int N_max, int C_max) { return make_layout(N_max, C_m
 
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream) {
   const Layout L = make_layout(p.N_max, p.C_max);
-  int rc = allow_lds((const void*)transform_kernel, L.bytes);
+  // one wavefront per 256 rows of the larger capacity, at most kTfMaxWaves
+  // (eight were measured fastest on genomes of up to 535 nodes / 1894
+  // connections: 4 and 16 slower)
+  int waves = 1;
+  while (waves < kTfMaxWaves && waves * 256 < std::max(p.N_max, p.C_max)) waves *= 2;
+  const void* k = waves == 1 ? (const void*)transform_kernel<1>
+                             : (const void*)transform_kernel<kTfMaxWaves>;
+  int rc = allow_lds(k, L.bytes);
   if (rc != TN_OK || p.P == 0) return rc;
-  hipLaunchKernelGGL(transform_kernel, dim3(p.P), dim3(kWave), L.bytes, stream,
-                     make_view(p), make_view(t), L);
+  if (waves == 1)
+    hipLaunchKernelGGL(transform_kernel<1>, dim3(p.P), dim3(kWave), L.bytes, stream,
+                       make_view(p), make_view(t), L);
+  else
+    hipLaunchKernelGGL(transform_kernel<kTfMaxWaves>, dim3(p.P), dim3(kWave * waves), L.bytes,
+                       stream, make_view(p), make_view(t), L);
   return check_launch();
 }
 
