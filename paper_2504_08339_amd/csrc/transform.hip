@@ -23,6 +23,7 @@
 //      evaluated concurrently.
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "tn_internal.hpp"
 
@@ -48,6 +49,11 @@ __device__ __forceinline__ uint32_t hash64(unsigned long long k) {
 }
 
 struct Layout {
+  // genomes this launch takes: node rows <= n_cap and connection rows <= c_cap,
+  // and not both within (n_prev, c_prev) (an earlier launch's); the launch
+  // with the population's capacities also takes the oversize genomes
+  int n_cap, c_cap, n_prev, c_prev;
+  bool last;
   int HN, HC;              // hash table sizes (powers of two)
   int off_hkey, off_hslot, off_nkey, off_deg, off_rem, off_outdeg, off_pos,
       off_order, off_level, off_ptr, off_cursor, off_outlist, off_esrc, off_edst,
@@ -63,6 +69,10 @@ int next_pow2(int x) {
 
 Layout make_layout(int N, int C) {
   Layout L;
+  L.n_cap = N;
+  L.c_cap = C;
+  L.n_prev = L.c_prev = -1;
+  L.last = true;
   L.HN = next_pow2(2 * N);
   L.HC = next_pow2(2 * C);
   size_t o = 0;
@@ -138,6 +148,8 @@ __device__ void write_flagged(const PopView& pop, const TrView& tr, int g, int s
 }
 
 constexpr int kTfMaxWaves = 8;
+// Ragged populations of at least this many genomes are transformed by size class.
+constexpr int kTfClassMinGenomes = 2048;
 
 // Workgroup barrier that orders LDS accesses only: the kernel never reads back
 // what it stores to global memory, so its stores stay in flight across it.
@@ -250,7 +262,12 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
   const int64_t cb = pop.conn_base(g);
   const int64_t nrows64 = pop.node_rows(g);
   const int64_t crows64 = pop.conn_rows(g);
-  if (nrows64 > N || crows64 > C || nrows64 < 0 || crows64 < 0) {
+  const bool bad = nrows64 > N || crows64 > C || nrows64 < 0 || crows64 < 0;
+  if (bad ? !L.last
+          : (nrows64 <= L.n_prev && crows64 <= L.c_prev) ||
+                (!L.last && (nrows64 > L.n_cap || crows64 > L.c_cap)))
+    return;  // another launch's genome
+  if (bad) {
     write_flagged(pop, tr, g, TN_OVERSIZE, nb, nrows64 > 0 ? nrows64 : 0, cb,
                   crows64 > 0 ? crows64 : 0);
     return;
@@ -727,23 +744,51 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
 size_t transform_lds_bytes(int N_max, int C_max) { return make_layout(N_max, C_max).bytes; }
 
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream) {
-  const Layout L = make_layout(p.N_max, p.C_max);
-  // one wavefront per 256 rows of the larger capacity, at most kTfMaxWaves
-  // (eight were measured fastest on genomes of up to 535 nodes / 1894
-  // connections: 4 and 16 slower)
-  int waves = 1;
-  while (waves < kTfMaxWaves && waves * 256 < std::max(p.N_max, p.C_max)) waves *= 2;
-  const void* k = waves == 1 ? (const void*)transform_kernel<1>
-                             : (const void*)transform_kernel<kTfMaxWaves>;
-  int rc = allow_lds(k, L.bytes);
-  if (rc != TN_OK || p.P == 0) return rc;
-  if (waves == 1)
-    hipLaunchKernelGGL(transform_kernel<1>, dim3(p.P), dim3(kWave), L.bytes, stream,
-                       make_view(p), make_view(t), L);
-  else
-    hipLaunchKernelGGL(transform_kernel<kTfMaxWaves>, dim3(p.P), dim3(kWave * waves), L.bytes,
-                       stream, make_view(p), make_view(t), L);
-  return check_launch();
+  // Size classes of a large ragged population: one launch per class, each with
+  // the LDS of its largest genome, so the many small genomes are not held to
+  // the few large ones' LDS (two workgroups per CU at 535 nodes / 1894
+  // connections). A padded population, or a small one, is one launch.
+  std::vector<Layout> cls;
+  if (p.node_off && p.P >= kTfClassMinGenomes) {
+    int n_prev = -1, c_prev = -1;
+    for (int n : {96, 192, 320}) {
+      const int c = std::min(p.C_max, 4 * n);
+      if (n >= p.N_max) break;
+      Layout L = make_layout(n, c);
+      L.last = false;
+      L.n_prev = n_prev;
+      L.c_prev = c_prev;
+      cls.push_back(L);
+      n_prev = n;
+      c_prev = c;
+    }
+    Layout L = make_layout(p.N_max, p.C_max);
+    L.n_prev = n_prev;
+    L.c_prev = c_prev;
+    cls.push_back(L);
+  } else {
+    cls.push_back(make_layout(p.N_max, p.C_max));
+  }
+  for (const Layout& L : cls) {
+    // one wavefront per 256 rows of the larger capacity, at most kTfMaxWaves
+    // (eight were measured fastest on genomes of up to 535 nodes / 1894
+    // connections: 4 and 16 slower)
+    int waves = 1;
+    while (waves < kTfMaxWaves && waves * 256 < std::max(L.n_cap, L.c_cap)) waves *= 2;
+    const void* k = waves == 1 ? (const void*)transform_kernel<1>
+                               : (const void*)transform_kernel<kTfMaxWaves>;
+    int rc = allow_lds(k, L.bytes);
+    if (rc != TN_OK || p.P == 0) return rc;
+    if (waves == 1)
+      hipLaunchKernelGGL(transform_kernel<1>, dim3(p.P), dim3(kWave), L.bytes, stream,
+                         make_view(p), make_view(t), L);
+    else
+      hipLaunchKernelGGL(transform_kernel<kTfMaxWaves>, dim3(p.P), dim3(kWave * waves),
+                         L.bytes, stream, make_view(p), make_view(t), L);
+    rc = check_launch();
+    if (rc != TN_OK) return rc;
+  }
+  return TN_OK;
 }
 
 }  // namespace tn

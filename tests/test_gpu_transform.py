@@ -103,6 +103,53 @@ def test_ragged_uneven_sizes():
     assert compare(padded, gp) == pop.P
 
 
+def test_large_ragged_population_by_size_class():
+    """A ragged population of 2200 uneven genomes (the library transforms one
+    of at least 2048 genomes in launches by size class): genomes appended
+    with hole connection rows, so that their connection rows and not their
+    node rows decide the class, and a node capacity below the largest genomes
+    (those are OVERSIZE). Statuses of every genome; every field bit-exact
+    against the oracle on the padded genomes, on both sides of each class
+    bound and on a random sample."""
+    base = synth.batching_population(P=2200)
+    rng = np.random.default_rng(77)
+    padded_ids = rng.choice(2200, size=40, replace=False)
+    nb, cb, n_off, c_off = [], [], [0], [0]
+    for g in range(base.P):
+        n = base.node_rows(g)
+        c = {k: v.copy() for k, v in base.conn_rows(g).items()}
+        if g in padded_ids:
+            extra = int(rng.integers(300, 700))   # holes: rows with in = out = -1
+            c = {k: np.concatenate([v, np.full(extra, -1 if k in ("in", "out") else 0, v.dtype)])
+                 for k, v in c.items()}
+        nb.append(n)
+        cb.append(c)
+        n_off.append(n_off[-1] + n["key"].shape[0])
+        c_off.append(c_off[-1] + c["in"].shape[0])
+    cat = lambda bl, k: np.concatenate([b[k] for b in bl])
+    rows = np.diff(n_off)
+    N_cap = int(np.sort(rows)[-5])                # the four largest genomes exceed it
+    pop = synth.Population(base.n_in, base.n_out, N_cap, int(np.diff(c_off).max()),
+                           cat(nb, "key"), cat(nb, "bias"), cat(nb, "resp"), cat(nb, "act"),
+                           cat(nb, "agg"), cat(cb, "in"), cat(cb, "out"), cat(cb, "w"), cat(cb, "en"),
+                           np.array(n_off, np.int64), np.array(c_off, np.int64))
+    got = run_transform(pop)
+    over = rows > N_cap
+    assert over.sum() == 4
+    assert (got["status"][:pop.P][over] == oracle.OVERSIZE).all()
+    assert (got["status"][:pop.P][~over] == 0).all()
+    crows = np.diff(c_off)
+    near = [g for g in range(pop.P) if any(abs(int(rows[g]) - b) <= 2 for b in (96, 192, 320))
+            or any(abs(int(crows[g]) - b) <= 8 for b in (384, 768, 1280))]
+    sample = sorted(set(padded_ids.tolist()) | set(near[:120]) |
+                    set(rng.choice(pop.P, size=120, replace=False).tolist()) |
+                    set(np.flatnonzero(over).tolist()))
+    assert compare(pop, got, sample) == len(sample) - int(over.sum())
+    for g in sample:
+        if not over[g]:
+            _check_rows(pop, got, g)
+
+
 def test_ragged_oversize():
     pop = synth.to_ragged(synth.control_population(P=50))
     small = synth.Population(**{**pop.__dict__, "N_max": 40, "C_max": 170})
