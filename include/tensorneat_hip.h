@@ -289,8 +289,10 @@ typedef struct tn_transformed_elems {
 int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out);
 
 /* Transformation of every genome (Section 3.3; BaseGenome.transform of
- * Appendix B, batched over the population). One launch, one wavefront per
- * genome. Fills every array of *tr. */
+ * Appendix B, batched over the population). One workgroup per genome (one to
+ * eight wavefronts, by the population's row capacities); a ragged population
+ * of at least 2048 genomes takes one launch per size class, all on `stream`.
+ * Fills every array of *tr; the results do not depend on the launch shape. */
 int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t stream);
 
 /* ------------------------------------------------------ the calculation */
