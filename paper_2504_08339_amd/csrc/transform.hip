@@ -402,29 +402,89 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
 
   // 5. level-synchronous Kahn rounds; a round's rows are placed in ascending
   // row order
+  __shared__ uint32_t free_bits[TN_MAX_NODES / 32];  // here: rows ready for the next round
   int emitted = 0;
-  for (int lvl = 0;; ++lvl) {
-    const int start = emitted;
-    for (int base = 0; base < nrows; base += T) {
-      const int i = base + tid;
-      const bool ready = i < nrows && nkey[i] >= 0 && pos_of[i] < 0 && rem[i] == 0;
-      int cnt;
-      const int ex = G.excl_count(ready, &cnt);
-      if (ready) {
-        const int p = emitted + ex;
-        pos_of[i] = (int16_t)p;
-        order_l[p] = (int16_t)i;
-        level_l[p] = (int16_t)lvl;
+  if constexpr (kW == 1) {
+    // one wavefront: each round tests every row
+    for (int lvl = 0;; ++lvl) {
+      const int start = emitted;
+      for (int base = 0; base < nrows; base += T) {
+        const int i = base + tid;
+        const bool ready = i < nrows && nkey[i] >= 0 && pos_of[i] < 0 && rem[i] == 0;
+        int cnt;
+        const int ex = G.excl_count(ready, &cnt);
+        if (ready) {
+          const int p = emitted + ex;
+          pos_of[i] = (int16_t)p;
+          order_l[p] = (int16_t)i;
+          level_l[p] = (int16_t)lvl;
+        }
+        emitted += cnt;
       }
-      emitted += cnt;
+      if (emitted == start) break;
+      G.sync();
+      for (int p = start + tid; p < emitted; p += T) {
+        const int s = order_l[p];
+        for (int j = ptr[s]; j < ptr[s + 1]; ++j) atomicSub(&rem[outlist[j]], 1);
+      }
+      G.sync();
     }
-    if (emitted == start) break;
+  } else {
+    // the rounds on the first wavefront: the rows ready for the next round
+    // are the bits of a bitmap, set when a row's last in-edge is removed; a
+    // round places them in ascending row order (lane w expands word w at its
+    // prefix offset), without testing every row
+    uint32_t* ready = free_bits;
+    for (int w = tid; w < TN_MAX_NODES / 32; w += T) ready[w] = 0u;
     G.sync();
-    for (int p = start + tid; p < emitted; p += T) {
-      const int s = order_l[p];
-      for (int j = ptr[s]; j < ptr[s + 1]; ++j) atomicSub(&rem[outlist[j]], 1);
+    for (int i = tid; i < nrows; i += T)
+      if (nkey[i] >= 0 && rem[i] == 0) atomicOr(&ready[i >> 5], 1u << (i & 31));
+    G.sync();
+    if (tid < kWave) {
+      const int lane = tid;
+      int done = 0;
+      for (int lvl = 0;; ++lvl) {
+        const uint32_t bits = lane < TN_MAX_NODES / 32 ? ready[lane] : 0u;
+        const int c = __popc(bits);
+        const int incl = wave_inclusive_scan(c);
+        const int cnt = __shfl(incl, kWave - 1, kWave);
+        if (cnt == 0) break;
+        int o = done + incl - c;
+        for (uint32_t x = bits; x != 0u; x &= x - 1, ++o) {
+          const int i = lane * 32 + (__ffs(x) - 1);
+          pos_of[i] = (int16_t)o;
+          order_l[o] = (int16_t)i;
+          level_l[o] = (int16_t)lvl;
+        }
+        if (lane < TN_MAX_NODES / 32) ready[lane] = 0u;
+        const int start = done;
+        done += cnt;
+        wave_sync();
+        for (int p = start + lane; p < done; p += kWave) {
+          const int s = order_l[p];
+          const int j1 = ptr[s + 1];
+          int j = ptr[s];
+          for (; j + 4 <= j1; j += 4) {  // four removals in flight
+            const int d0 = outlist[j], d1 = outlist[j + 1], d2 = outlist[j + 2],
+                      d3 = outlist[j + 3];
+            const int r0 = atomicSub(&rem[d0], 1), r1 = atomicSub(&rem[d1], 1),
+                      r2 = atomicSub(&rem[d2], 1), r3 = atomicSub(&rem[d3], 1);
+            if (r0 == 1) atomicOr(&ready[d0 >> 5], 1u << (d0 & 31));
+            if (r1 == 1) atomicOr(&ready[d1 >> 5], 1u << (d1 & 31));
+            if (r2 == 1) atomicOr(&ready[d2 >> 5], 1u << (d2 & 31));
+            if (r3 == 1) atomicOr(&ready[d3 >> 5], 1u << (d3 & 31));
+          }
+          for (; j < j1; ++j) {
+            const int d = outlist[j];
+            if (atomicSub(&rem[d], 1) == 1) atomicOr(&ready[d >> 5], 1u << (d & 31));
+          }
+        }
+        wave_sync();
+      }
+      if (lane == 0) flags = done;  // the status word has been read; it carries the count
     }
     G.sync();
+    emitted = flags;
   }
   if (emitted < n_valid) {
     write_flagged(pop, tr, g, TN_CYCLE, nb, nrows, cb, crows);
@@ -505,16 +565,26 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
 
   // 9. value rows with reuse (see the header). last[s]: position of the last
   // consumer of s (-1: none; outputs never free their row).
-  __shared__ uint32_t free_bits[TN_MAX_NODES / 32];
   __shared__ int next_row;
-  int32_t* last = deg;  // both are free now
+  int32_t* last = deg;        // both are free now
   int32_t* row = rem;
+  int32_t* fl_end = outdeg;   // per level: end of the list of rows it frees
+  int32_t* fl_list = cursor;  // positions whose row is freed, by level
   for (int p = tid; p < n_valid; p += T) last[p] = -1;
+  for (int l = tid; l < n_levels; l += T) fl_end[l] = 0;
   for (int w = tid; w < TN_MAX_NODES / 32; w += T) free_bits[w] = 0u;
   G.sync();
   for (int p = tid; p < n_valid; p += T)
     for (int j = ptr[p]; j < ptr[p + 1]; ++j) atomicMax(&last[csr_src[j]], p);
   G.sync();
+  // The level after which the row of position p is freed: that of its last
+  // consumer, or its own for a non-input position nothing reads; never for an
+  // output, nor for an input nobody reads (free from the start).
+  auto free_level = [&](int p, int k) {
+    if (k >= pop.n_in && k < nio) return -1;
+    if (last[p] >= 0) return (int)level_l[last[p]];
+    return k >= pop.n_in ? (int)level_l[p] : -1;
+  };
   // input k takes row k; an input nobody reads is free at once
   for (int p = tid; p < n_valid; p += T) {
     const int k = nkey[order_l[p]];
@@ -522,51 +592,73 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
       row[p] = k;
       if (last[p] < 0) atomicOr(&free_bits[k >> 5], 1u << (k & 31));
     }
+    const int fl = free_level(p, k);
+    if (fl >= 0) atomicAdd(&fl_end[fl], 1);
   }
   if (tid == 0) next_row = pop.n_in;
   G.sync();
-  for (int l = 0; l < n_levels; ++l) {
-    const int lb = lstart[l], le = lstart[l + 1];
-    // allocate the level's non-input positions, in order: the i-th takes the
-    // i-th lowest free row, or a new one once the free rows are used up
-    for (int base = lb; base < le; base += T) {
-      const int p = base + tid;
-      const bool node = p < le && nkey[order_l[p]] >= pop.n_in;
-      int k;
-      const int i = G.excl_count(node, &k);
-      if (k == 0) continue;
-      int nfree = 0;
-      for (int w = 0; w < TN_MAX_NODES / 32; ++w) nfree += __popc(free_bits[w]);
-      const int nr = next_row;
-      if (node) {
-        int r;
-        if (i < nfree) {
-          int skip = i, w = 0;
-          while (__popc(free_bits[w]) <= skip) skip -= __popc(free_bits[w++]);
-          uint32_t x = free_bits[w];
-          for (int t = 0; t < skip; ++t) x &= x - 1;
-          r = w * 32 + (__ffs(x) - 1);
-        } else {
-          r = nr + (i - nfree);
-        }
-        row[p] = r;
-      }
-      G.sync();
-      if (node && i < nfree) atomicAnd(&free_bits[row[p] >> 5], ~(1u << (row[p] & 31)));
-      if (tid == 0 && k > nfree) next_row = nr + (k - nfree);
-      G.sync();
+  {
+    int carry = 0;  // counts -> start offsets
+    for (int base = 0; base < n_levels; base += T) {
+      const int l = base + tid;
+      const int c = l < n_levels ? fl_end[l] : 0;
+      int tot;
+      const int ex = G.excl_sum(c, &tot);
+      if (l < n_levels) fl_end[l] = carry + ex;
+      carry += tot;
     }
-    // free the rows whose last consumer sits in this level, and those of this
-    // level's positions that nothing reads
-    for (int q = tid; q < n_valid; q += T) {
-      const int key = nkey[order_l[q]];
-      const bool is_out = key >= pop.n_in && key < pop.n_in + pop.n_out;
-      const bool dead_here = last[q] < 0 && key >= pop.n_in && q >= lb && q < le;
-      if (!is_out && ((last[q] >= lb && last[q] < le) || dead_here))
-        atomicOr(&free_bits[row[q] >> 5], 1u << (row[q] & 31));
-    }
-    G.sync();
   }
+  G.sync();
+  for (int p = tid; p < n_valid; p += T) {  // start offsets -> ends
+    const int fl = free_level(p, nkey[order_l[p]]);
+    if (fl >= 0) fl_list[atomicAdd(&fl_end[fl], 1)] = p;
+  }
+  G.sync();
+  // level by level, on the first wavefront (its own syncs only)
+  if (tid < kWave) {
+    const int lane = tid;
+    for (int l = 0; l < n_levels; ++l) {
+      const int lb = lstart[l], le = lstart[l + 1];
+      // allocate the level's non-input positions, in order: the i-th takes
+      // the i-th lowest free row, or a new one once the free rows are used up
+      for (int base = lb; base < le; base += kWave) {
+        const int p = base + lane;
+        const bool node = p < le && nkey[order_l[p]] >= pop.n_in;
+        const uint64_t m = __ballot(node);
+        const int k = __popcll(m);
+        if (k == 0) continue;
+        const int i = mbcnt(m);
+        int nfree = 0;
+        for (int w = 0; w < TN_MAX_NODES / 32; ++w) nfree += __popc(free_bits[w]);
+        const int nr = next_row;
+        if (node) {
+          int r;
+          if (i < nfree) {
+            int skip = i, w = 0;
+            while (__popc(free_bits[w]) <= skip) skip -= __popc(free_bits[w++]);
+            uint32_t x = free_bits[w];
+            for (int t = 0; t < skip; ++t) x &= x - 1;
+            r = w * 32 + (__ffs(x) - 1);
+          } else {
+            r = nr + (i - nfree);
+          }
+          row[p] = r;
+        }
+        wave_sync();
+        if (node && i < nfree) atomicAnd(&free_bits[row[p] >> 5], ~(1u << (row[p] & 31)));
+        if (lane == 0 && k > nfree) next_row = nr + (k - nfree);
+        wave_sync();
+      }
+      // free the rows whose last consumer sits in this level, and those of
+      // this level's positions that nothing reads
+      for (int j = (l ? fl_end[l - 1] : 0) + lane; j < fl_end[l]; j += kWave) {
+        const int q = fl_list[j];
+        atomicOr(&free_bits[row[q] >> 5], 1u << (row[q] & 31));
+      }
+      wave_sync();
+    }
+  }
+  G.sync();
   for (int p = tid; p < nrows; p += T) tr.pos_row[nb + p] = p < n_valid ? row[p] : -1;
   G.sync();
 
