@@ -404,8 +404,10 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
   // row order
   __shared__ uint32_t free_bits[TN_MAX_NODES / 32];  // here: rows ready for the next round
   int emitted = 0;
-  if constexpr (kW == 1) {
-    // one wavefront: each round tests every row
+  bool scan = true;
+  if constexpr (kW > 1) scan = nrows <= T;
+  if (scan) {
+    // each round tests every row (one pass of the workgroup when the rows fit)
     for (int lvl = 0;; ++lvl) {
       const int start = emitted;
       for (int base = 0; base < nrows; base += T) {
@@ -425,15 +427,26 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
       G.sync();
       for (int p = start + tid; p < emitted; p += T) {
         const int s = order_l[p];
-        for (int j = ptr[s]; j < ptr[s + 1]; ++j) atomicSub(&rem[outlist[j]], 1);
+        const int j1 = ptr[s + 1];
+        int j = ptr[s];
+        for (; j + 4 <= j1; j += 4) {  // four removals in flight
+          const int d0 = outlist[j], d1 = outlist[j + 1], d2 = outlist[j + 2],
+                    d3 = outlist[j + 3];
+          atomicSub(&rem[d0], 1);
+          atomicSub(&rem[d1], 1);
+          atomicSub(&rem[d2], 1);
+          atomicSub(&rem[d3], 1);
+        }
+        for (; j < j1; ++j) atomicSub(&rem[outlist[j]], 1);
       }
       G.sync();
     }
   } else {
-    // the rounds on the first wavefront: the rows ready for the next round
-    // are the bits of a bitmap, set when a row's last in-edge is removed; a
-    // round places them in ascending row order (lane w expands word w at its
-    // prefix offset), without testing every row
+    // more rows than threads (a padded population): the rounds on the first
+    // wavefront, the rows ready for the next round the bits of a bitmap, set
+    // when a row's last in-edge is removed; a round places them in ascending
+    // row order (lane w expands word w at its prefix offset), without testing
+    // every row
     uint32_t* ready = free_bits;
     for (int w = tid; w < TN_MAX_NODES / 32; w += T) ready[w] = 0u;
     G.sync();
