@@ -150,6 +150,72 @@ def test_large_ragged_population_by_size_class():
             _check_rows(pop, got, g)
 
 
+def _large_defective(rng):
+    """The 60 largest genomes of a 400-genome batching population, padded with
+    room for extra rows, with defects injected into the first six: a two-node
+    cycle, a duplicated connection, a dangling enabled connection, an enabled
+    connection into an input, a long cycle closing a path of several levels,
+    and a duplicated node key; the rest stay valid."""
+    base = synth.batching_population(P=400)
+    sizes = np.diff(base.node_off)
+    big = synth.subset(base, np.argsort(-sizes, kind="stable")[:60])
+    pop = synth.to_padded(big, N_max=big.N_max + 2, C_max=big.C_max + 4)
+
+    def add_conn(g, a, b, en=1):
+        r = int(np.flatnonzero(pop.conn_in[g] < 0)[0])
+        pop.conn_in[g, r], pop.conn_out[g, r] = a, b
+        pop.conn_w[g, r], pop.conn_en[g, r] = 0.5, en
+
+    def edges(g):
+        m = (pop.conn_in[g] >= 0) & (pop.conn_en[g] > 0)
+        return list(zip(pop.conn_in[g][m].tolist(), pop.conn_out[g][m].tolist()))
+
+    io = pop.n_in + pop.n_out
+    hidden_edges = lambda g: [(a, b) for a, b in edges(g) if a >= io and b >= io]
+    a, b = hidden_edges(0)[0]
+    assert (b, a) not in edges(0)
+    add_conn(0, b, a)                                          # two-node cycle
+    r = int(np.flatnonzero(pop.conn_in[1] >= 0)[0])
+    add_conn(1, int(pop.conn_in[1, r]), int(pop.conn_out[1, r]), en=0)   # duplicate marking
+    add_conn(2, 10 ** 6, int(pop.node_key[2][pop.node_key[2] >= io][0]))  # dangling
+    add_conn(3, int(pop.node_key[3][pop.node_key[3] >= io][0]), 0)         # into an input
+    succ = {}
+    for x, y in edges(4):
+        succ.setdefault(x, []).append(y)
+    a, b = hidden_edges(4)[0]
+    path = [a, b]
+    while path[-1] in succ and len(path) < 12:
+        path.append(succ[path[-1]][0])
+    add_conn(4, path[-1], a)                                   # closes a path of len(path)
+    assert len(path) >= 4
+    h = int(np.flatnonzero(pop.node_key[5] >= io)[0])
+    e = int(np.flatnonzero(pop.node_key[5] < 0)[0])
+    for k in ("key", "bias", "resp", "act", "agg"):            # duplicate node key
+        getattr(pop, "node_" + k)[5, e] = getattr(pop, "node_" + k)[5, h]
+    return pop
+
+
+def test_large_genomes_defects_padded_and_ragged():
+    """Defects in genomes of 500+ rows, where a workgroup of eight wavefronts
+    takes a genome and, padded, its Kahn rounds run from the ready bitmap
+    (more rows than threads): statuses equal the oracle's, and the valid
+    genomes' fields are bit-exact; the same genomes in the ragged layout."""
+    pop = _large_defective(np.random.default_rng(3))
+    assert pop.N_max > 512
+    want = oracle.transform_arrays(pop)["status"]
+    assert sorted(set(int(x) for x in want[:6])) == sorted({oracle.CYCLE, oracle.DUP_CONN,
+                                                           oracle.DANGLING, oracle.INPUT_DST,
+                                                           oracle.DUP_NODE})
+    assert (np.array(want[6:]) == 0).all()
+    got = run_transform(pop)
+    assert compare(pop, got) == pop.P - 6
+    for g in range(6, pop.P):
+        _check_rows(pop, got, g)
+    rag = synth.to_ragged(pop)
+    got = run_transform(rag)
+    assert compare(rag, got) == rag.P - 6
+
+
 def test_ragged_oversize():
     pop = synth.to_ragged(synth.control_population(P=50))
     small = synth.Population(**{**pop.__dict__, "N_max": 40, "C_max": 170})
