@@ -64,7 +64,7 @@ Layout layout(int N, int C, int nio) {
   l.S = next_pow2(C);
   l.phase1 = 8 * (size_t)l.HN + 8 * (size_t)l.HM + 4 * (size_t)l.S;
   l.vals = 2 * (size_t)N * kWave * sizeof(float);
-  const size_t p = 4 * ((size_t)N + 1) + 8 * (size_t)C + 12 * (size_t)N + 4 * (size_t)nio;
+  const size_t p = 4 * ((size_t)N + 1) + 8 * (size_t)C + 16 * (size_t)N + 4 * (size_t)nio;
   l.persist = (p + 15) & ~size_t(15);
   l.total = l.persist + std::max(l.phase1, l.vals);
   return l;
@@ -77,19 +77,20 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
                                                            size_t persist) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int status;
+  __shared__ int n_act;  // entries of alist
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
   const int N = pop.N_max, C = pop.C_max, n_in = pop.n_in, n_out = pop.n_out;
   const int nio = n_in + n_out;
   // kept tables
-  int32_t* rp = (int32_t*)smem;                 // [N + 1] in-edges of node row r
-  int32_t* esrc = rp + N + 1;                   // [C] source node row
-  float* ew = (float*)(esrc + C);               // [C] weight
-  float* nbias = ew + C;                        // [N]
+  int2* edge = (int2*)smem;                     // [C] in-edge: source row * 64, weight bits
+  int32_t* rp = (int32_t*)(edge + C);           // [N + 1] in-edges of node row r
+  float* nbias = (float*)(rp + N + 1);          // [N]
   float* nresp = nbias + N;                     // [N]
   int32_t* nfn = (int32_t*)(nresp + N);         // [N] act | agg << 8; input: bit 31 | index
   int32_t* iorow = nfn + N;                     // [n_in + n_out] node row of key k
+  int32_t* alist = iorow + nio;                 // [N] the rows a sweep computes
   unsigned char* region = smem + persist;
   // phase 1 region
   int32_t* hk = (int32_t*)region;               // [HN] node keys
@@ -101,7 +102,10 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
 
   const int64_t nb = pop.node_base(g), cb = pop.conn_base(g);
   const int64_t nrows = pop.node_rows(g), crows = pop.conn_rows(g);
-  if (tid == 0) status = 0;
+  if (tid == 0) {
+    status = 0;
+    n_act = 0;
+  }
   for (int h = tid; h < HN; h += kBlock) {
     hk[h] = -1;
     hr[h] = 0x7fffffff;
@@ -222,8 +226,8 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
     const int32_t key = skey[i];
     if (key == kSortPad) continue;
     const int row = key & 0xfff;
-    esrc[i] = row_of(pop.conn_in[cb + row]);
-    ew[i] = pop.conn_w[cb + row];
+    edge[i] = make_int2(row_of(pop.conn_in[cb + row]) * kWave,
+                        __float_as_int(pop.conn_w[cb + row]));
   }
   for (int r = tid; r < N; r += kBlock) {
     const int32_t k = r < nrows ? pop.node_key[nb + r] : -1;
@@ -233,10 +237,13 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
     nfn[r] = f;
     nbias[r] = r < nrows ? pop.node_bias[nb + r] : 0.0f;
     nresp[r] = r < nrows ? pop.node_resp[nb + r] : 0.0f;
+    // the computed rows, in any order (the rows of a sweep are independent)
+    if (f >= 0 && f != kRowEmpty) alist[atomicAdd(&n_act, 1)] = r;
   }
   if (status_out && tid == 0) status_out[g] = 0;
   __syncthreads();  // phase 1 region is reused for the values from here on
 
+  const int na = __builtin_amdgcn_readfirstlane(n_act);
   const float* x_g = obs + (int64_t)g * obs_stride;
   float* out_g = out + (int64_t)g * B * n_out;
   for (int b0 = 0; b0 < B; b0 += kWave) {
@@ -254,21 +261,35 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
     for (int t = 0; t < T; ++t) {
       const float* cur = vals + (size_t)(t & 1) * N * kWave;
       float* nxt = vals + (size_t)((t + 1) & 1) * N * kWave;
-      for (int r = wv; r < N; r += kWaves) {
-        const int32_t f = nfn[r];
-        if (f < 0 || f == kRowEmpty) continue;  // input or empty row
-        const int e0 = rp[r], e1 = rp[r + 1];
+      // the computed rows, dealt round-robin to the wavefronts; the row, its
+      // function word and in-edge range as wavefront-uniform values (scalar
+      // loop control and branches)
+      for (int i = wv; i < na; i += kWaves) {
+        const int r = __builtin_amdgcn_readfirstlane(alist[i]);
+        const int32_t f = __builtin_amdgcn_readfirstlane(nfn[r]);
+        const int e0 = __builtin_amdgcn_readfirstlane(rp[r]);
+        const int e1 = __builtin_amdgcn_readfirstlane(rp[r + 1]);
         const int agg = (f >> 8) & 0xff;
         float s;
         if (agg == TN_AGG_SUM) {
           s = 0.0f;
-          for (int e = e0; e < e1; ++e) s = fmaf(ew[e], cur[esrc[e] * kWave + lane], s);
+          int e = e0;
+          for (; e + 2 <= e1; e += 2) {  // two in-edges' records, then both values
+            const int2 q0 = edge[e], q1 = edge[e + 1];
+            const float x0 = cur[q0.x + lane], x1 = cur[q1.x + lane];
+            s = fmaf(__int_as_float(q0.y), x0, s);
+            s = fmaf(__int_as_float(q1.y), x1, s);
+          }
+          if (e < e1) {
+            const int2 q = edge[e];
+            s = fmaf(__int_as_float(q.y), cur[q.x + lane], s);
+          }
         } else if (e0 == e1) {
           s = 0.0f;
         } else {
-          s = ew[e0] * cur[esrc[e0] * kWave + lane];
+          s = __int_as_float(edge[e0].y) * cur[edge[e0].x + lane];
           for (int e = e0 + 1; e < e1; ++e) {
-            const float q = ew[e] * cur[esrc[e] * kWave + lane];
+            const float q = __int_as_float(edge[e].y) * cur[edge[e].x + lane];
             switch (agg) {
               case TN_AGG_PRODUCT: s = s * q; break;
               case TN_AGG_MAX: s = fmaxf(s, q); break;
