@@ -11,11 +11,13 @@
 //      an input, attribute codes in range; any failure: NaN outputs;
 //   2. the enabled in-edges grouped by destination node row in ascending
 //      connection row (one bitonic sort of dst_row << 12 | conn_row in LDS),
-//      each with its source node row and weight;
+//      each as one 8-byte record (source row offset, weight); one 16-byte
+//      record per computed (non-input) row: function word with the row, its
+//      in-edge range, bias, response;
 //   3. tiles of 64 observations (one per lane): two LDS value buffers of
 //      N_max rows x 64, read from one and written to the other each sweep; the
-//      node rows are dealt round-robin to the four wavefronts, one barrier per
-//      sweep.
+//      computed rows' records are dealt round-robin to the four wavefronts,
+//      one barrier per sweep.
 // The sum aggregation accumulates with fused multiply-adds in ascending
 // in-edge order and z = fma(response, aggregate, bias), as in the feedforward
 // engines, so on an acyclic sum-aggregation genome T sweeps past its largest
@@ -64,7 +66,7 @@ Layout layout(int N, int C, int nio) {
   l.S = next_pow2(C);
   l.phase1 = 8 * (size_t)l.HN + 8 * (size_t)l.HM + 4 * (size_t)l.S;
   l.vals = 2 * (size_t)N * kWave * sizeof(float);
-  const size_t p = 4 * ((size_t)N + 1) + 8 * (size_t)C + 16 * (size_t)N + 4 * (size_t)nio;
+  const size_t p = 16 * (size_t)N + 8 * (size_t)C + 4 * (size_t)N + 4 * (size_t)nio;
   l.persist = (p + 15) & ~size_t(15);
   l.total = l.persist + std::max(l.phase1, l.vals);
   return l;
@@ -77,20 +79,18 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
                                                            size_t persist) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int status;
-  __shared__ int n_act;  // entries of alist
+  __shared__ int n_act;  // entries of crec
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = lane_id(), wv = wave_id();
   const int N = pop.N_max, C = pop.C_max, n_in = pop.n_in, n_out = pop.n_out;
   const int nio = n_in + n_out;
   // kept tables
-  int2* edge = (int2*)smem;                     // [C] in-edge: source row * 64, weight bits
-  int32_t* rp = (int32_t*)(edge + C);           // [N + 1] in-edges of node row r
-  float* nbias = (float*)(rp + N + 1);          // [N]
-  float* nresp = nbias + N;                     // [N]
-  int32_t* nfn = (int32_t*)(nresp + N);         // [N] act | agg << 8; input: bit 31 | index
+  int4* crec = (int4*)smem;                     // [N] computed row: act | agg << 8 | row << 16,
+                                                //     e0 | e1 << 16, bias bits, response bits
+  int2* edge = (int2*)(crec + N);               // [C] in-edge: source row * 64, weight bits
+  int32_t* nfn = (int32_t*)(edge + C);          // [N] act | agg << 8; input: bit 31 | index
   int32_t* iorow = nfn + N;                     // [n_in + n_out] node row of key k
-  int32_t* alist = iorow + nio;                 // [N] the rows a sweep computes
   unsigned char* region = smem + persist;
   // phase 1 region
   int32_t* hk = (int32_t*)region;               // [HN] node keys
@@ -211,17 +211,6 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
       __syncthreads();
     }
   }
-  // CSR: rp[r] = first sorted entry with destination row >= r
-  for (int r = tid; r <= N; r += kBlock) {
-    int lo = 0, hi = S;
-    const int32_t want = r << 12;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (skey[mid] < want) lo = mid + 1;
-      else hi = mid;
-    }
-    rp[r] = lo;
-  }
   for (int i = tid; i < S && i < C; i += kBlock) {
     const int32_t key = skey[i];
     if (key == kSortPad) continue;
@@ -235,10 +224,23 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
     if (k >= 0 && k < n_in) f = (int32_t)(kFnInput | (uint32_t)k);
     else if (k >= 0) f = pop.node_act[nb + r] | (pop.node_agg[nb + r] << 8);
     nfn[r] = f;
-    nbias[r] = r < nrows ? pop.node_bias[nb + r] : 0.0f;
-    nresp[r] = r < nrows ? pop.node_resp[nb + r] : 0.0f;
-    // the computed rows, in any order (the rows of a sweep are independent)
-    if (f >= 0 && f != kRowEmpty) alist[atomicAdd(&n_act, 1)] = r;
+    // the computed rows' records, in any order (the rows of a sweep are
+    // independent); in-edges e0 .. e1-1 from the sorted keys
+    if (f >= 0 && f != kRowEmpty) {
+      auto first = [&](int32_t want) {
+        int lo = 0, hi = S;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (skey[mid] < want) lo = mid + 1;
+          else hi = mid;
+        }
+        return lo;
+      };
+      const int e0 = first(r << 12), e1 = first((r + 1) << 12);
+      crec[atomicAdd(&n_act, 1)] =
+          make_int4(f | (r << 16), e0 | (e1 << 16), __float_as_int(pop.node_bias[nb + r]),
+                    __float_as_int(pop.node_resp[nb + r]));
+    }
   }
   if (status_out && tid == 0) status_out[g] = 0;
   __syncthreads();  // phase 1 region is reused for the values from here on
@@ -265,10 +267,12 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
       // function word and in-edge range as wavefront-uniform values (scalar
       // loop control and branches)
       for (int i = wv; i < na; i += kWaves) {
-        const int r = __builtin_amdgcn_readfirstlane(alist[i]);
-        const int32_t f = __builtin_amdgcn_readfirstlane(nfn[r]);
-        const int e0 = __builtin_amdgcn_readfirstlane(rp[r]);
-        const int e1 = __builtin_amdgcn_readfirstlane(rp[r + 1]);
+        const int4 q = crec[i];  // one 16-byte read
+        const int fr = __builtin_amdgcn_readfirstlane(q.x);
+        const int er = __builtin_amdgcn_readfirstlane(q.y);
+        const int32_t f = fr & 0xffff;
+        const int r = fr >> 16;
+        const int e0 = er & 0xffff, e1 = er >> 16;
         const int agg = (f >> 8) & 0xff;
         float s;
         if (agg == TN_AGG_SUM) {
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
           }
           if (agg == TN_AGG_MEAN) s = s / (float)(e1 - e0);
         }
-        float z[1] = {fmaf(nresp[r], s, nbias[r])}, v[1];
+        float z[1] = {fmaf(__int_as_float(q.w), s, __int_as_float(q.z))}, v[1];
         activate_all<1>(f & 0xff, z, v);
         nxt[r * kWave + lane] = v[0];
       }
