@@ -153,7 +153,7 @@ def build_host_sanitized(verbose: bool = False) -> str:
 
     def one(src):
         obj = os.path.join(out_dir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *flags, "-c", src, "-o", obj]
+        cmd = [hipcc(), *flags, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{res.stderr}")
