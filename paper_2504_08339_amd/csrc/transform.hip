@@ -74,7 +74,7 @@ Layout make_layout(int N, int C) {
   L.n_prev = L.c_prev = -1;
   L.last = true;
   L.HN = next_pow2(2 * N);
-  L.HC = next_pow2(2 * C);
+  L.HC = next_pow2(C + C / 4 + 1);  // marking hash at most 80 % full
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
