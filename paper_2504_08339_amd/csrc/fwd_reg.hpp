@@ -237,10 +237,12 @@ struct LaneRec {
 // The register-file walk over the 16-word records of the non-input positions
 // (tn_transformed.prog_rec), in topological order, for every tile of the
 // wavefront. The records come four at a time with one coalesced vector load
-// (64 lanes x one word), each block requested two blocks ahead: vector loads
-// complete in order, so that load overlaps eight nodes of work without holding
-// anything else up, and its words reach the scalar unit through v_readlane
-// with constant lane indexes. Lanes past the genome's last
+// (64 lanes x one word), each block requested two blocks ahead; the compiler
+// waits for it where the loop moves it to the next block's register, so a
+// load overlaps one block (four nodes) of work (blocks of eight records, whose
+// loads overlap eight nodes, measured no faster: the walk does not wait on
+// these loads). The words reach the scalar unit through v_readlane with
+// constant lane indexes. Lanes past the genome's last
 // record read its last word instead (no load past the genome's records).
 template <int R>
 __device__ __forceinline__ void walk_records(const int32_t* __restrict__ rec,
