@@ -291,7 +291,13 @@ int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out);
 /* Transformation of every genome (Section 3.3; BaseGenome.transform of
  * Appendix B, batched over the population). One workgroup per genome (one to
  * eight wavefronts, by the population's row capacities); a ragged population
- * of at least 2048 genomes takes one launch per size class, all on `stream`.
+ * of at least 2048 genomes takes one launch per size class. The largest class
+ * runs on `stream`, the others on side streams that the library creates once
+ * per device (default priority, non-blocking); they start after the work
+ * already queued on `stream` and `stream` waits for them before anything
+ * queued after this call, so the call is ordered on `stream` like a single
+ * launch (also under stream capture). Calls from several host threads are
+ * serialized while they queue their launches.
  * Fills every array of *tr; the results do not depend on the launch shape. */
 int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t stream);
 

@@ -23,6 +23,7 @@
 //      evaluated concurrently.
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <vector>
 
 #include "tn_internal.hpp"
@@ -848,6 +849,78 @@ __global__ __launch_bounds__(kWave * kW) void transform_kernel(PopView pop, TrVi
 
 size_t transform_lds_bytes(int N_max, int C_max) { return make_layout(N_max, C_max).bytes; }
 
+namespace {
+
+// The size classes of one call run side by side: the caller's stream takes
+// the largest class, side streams the others, forked from the caller's stream
+// and joined back to it with events, so the last, partly filled round of one
+// class's workgroups overlaps the others' work (the classes write disjoint
+// genomes). Side streams (default priority, non-blocking) and events are made
+// once per device; the mutex keeps the fork / launch / join sequence of one
+// call from interleaving with another's on the same events.
+constexpr int kTfMaxClasses = 4;
+constexpr int kMaxDevices = 64;
+struct ClassStreams {
+  hipStream_t side[kTfMaxClasses - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kTfMaxClasses - 1] = {};
+};
+std::mutex g_class_mu;
+ClassStreams g_class[kMaxDevices];
+bool g_class_ready[kMaxDevices] = {};
+
+// The current device's side streams and events (caller holds g_class_mu).
+int class_streams(ClassStreams** out) {
+  int dev = 0;
+  int rc = record_hip(hipGetDevice(&dev));
+  if (rc != TN_OK) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return TN_EUNSUPPORTED;
+  ClassStreams& cs = g_class[dev];
+  if (!g_class_ready[dev]) {
+    if (!cs.fork) rc = record_hip(hipEventCreateWithFlags(&cs.fork, hipEventDisableTiming));
+    for (int i = 0; i < kTfMaxClasses - 1 && rc == TN_OK; ++i) {
+      if (!cs.side[i]) rc = record_hip(hipStreamCreateWithFlags(&cs.side[i], hipStreamNonBlocking));
+      if (rc == TN_OK && !cs.join[i])
+        rc = record_hip(hipEventCreateWithFlags(&cs.join[i], hipEventDisableTiming));
+    }
+    if (rc != TN_OK) return rc;  // what was made is kept and completed next time
+    g_class_ready[dev] = true;
+  }
+  *out = &cs;
+  return TN_OK;
+}
+
+// Wavefronts per workgroup of a class: one per 256 rows of the larger
+// capacity, at most kTfMaxWaves (eight were measured fastest on genomes of up
+// to 535 nodes / 1894 connections: 4 and 16 slower).
+int class_waves(const Layout& L) {
+  int waves = 1;
+  while (waves < kTfMaxWaves && waves * 256 < std::max(L.n_cap, L.c_cap)) waves *= 2;
+  return waves;
+}
+
+int class_lds(const Layout& L) {
+  return allow_lds(class_waves(L) == 1 ? (const void*)transform_kernel<1>
+                                       : (const void*)transform_kernel<kTfMaxWaves>,
+                   L.bytes);
+}
+
+int launch_class(const tn_population& p, const tn_transformed& t, const Layout& L,
+                 hipStream_t stream) {
+  const int waves = class_waves(L);
+  const int rc = class_lds(L);
+  if (rc != TN_OK) return rc;
+  if (waves == 1)
+    hipLaunchKernelGGL(transform_kernel<1>, dim3(p.P), dim3(kWave), L.bytes, stream,
+                       make_view(p), make_view(t), L);
+  else
+    hipLaunchKernelGGL(transform_kernel<kTfMaxWaves>, dim3(p.P), dim3(kWave * waves), L.bytes,
+                       stream, make_view(p), make_view(t), L);
+  return check_launch();
+}
+
+}  // namespace
+
 int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_t stream) {
   // Size classes of a large ragged population: one launch per class, each with
   // the LDS of its largest genome, so the many small genomes are not held to
@@ -874,26 +947,32 @@ int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_
   } else {
     cls.push_back(make_layout(p.N_max, p.C_max));
   }
-  for (const Layout& L : cls) {
-    // one wavefront per 256 rows of the larger capacity, at most kTfMaxWaves
-    // (eight were measured fastest on genomes of up to 535 nodes / 1894
-    // connections: 4 and 16 slower)
-    int waves = 1;
-    while (waves < kTfMaxWaves && waves * 256 < std::max(L.n_cap, L.c_cap)) waves *= 2;
-    const void* k = waves == 1 ? (const void*)transform_kernel<1>
-                               : (const void*)transform_kernel<kTfMaxWaves>;
-    int rc = allow_lds(k, L.bytes);
-    if (rc != TN_OK || p.P == 0) return rc;
-    if (waves == 1)
-      hipLaunchKernelGGL(transform_kernel<1>, dim3(p.P), dim3(kWave), L.bytes, stream,
-                         make_view(p), make_view(t), L);
-    else
-      hipLaunchKernelGGL(transform_kernel<kTfMaxWaves>, dim3(p.P), dim3(kWave * waves),
-                         L.bytes, stream, make_view(p), make_view(t), L);
-    rc = check_launch();
-    if (rc != TN_OK) return rc;
+  if (p.P == 0) return class_lds(cls[0]);  // nothing to launch; the LDS check still applies
+  const int nc = (int)cls.size();
+  if (nc == 1) return launch_class(p, t, cls[0], stream);
+  if (nc > kTfMaxClasses) return TN_EUNSUPPORTED;
+
+  std::lock_guard<std::mutex> lock(g_class_mu);
+  ClassStreams* cs = nullptr;
+  int rc = class_streams(&cs);
+  if (rc == TN_OK) rc = record_hip(hipEventRecord(cs->fork, stream));
+  if (rc != TN_OK) return rc;
+  // largest class first, on the caller's stream
+  rc = launch_class(p, t, cls[nc - 1], stream);
+  int forked = 0;
+  for (int i = 0; i < nc - 1 && rc == TN_OK; ++i) {
+    rc = record_hip(hipStreamWaitEvent(cs->side[i], cs->fork, 0));
+    if (rc != TN_OK) break;
+    ++forked;
+    rc = launch_class(p, t, cls[i], cs->side[i]);
   }
-  return TN_OK;
+  // join every side stream that was forked, also after a failed launch
+  for (int i = 0; i < forked; ++i) {
+    int r = record_hip(hipEventRecord(cs->join[i], cs->side[i]));
+    if (r == TN_OK) r = record_hip(hipStreamWaitEvent(stream, cs->join[i], 0));
+    if (rc == TN_OK) rc = r;
+  }
+  return rc;
 }
 
 }  // namespace tn
