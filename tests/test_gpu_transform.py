@@ -12,14 +12,16 @@ from helpers import population_from_rows
 pytestmark = pytest.mark.gpu
 
 
+FIELDS = ("status", "n_valid", "order", "level", "row_ptr", "edge_src", "edge_row", "edge_w",
+          "pos_bias", "pos_resp", "pos_fn", "io_pos", "pos_row", "n_rows", "prog_node",
+          "prog_edge", "prog_rows", "prog_rec")
+
+
 def run_transform(pop):
     import paper_2504_08339_amd as tn
     dp = to_device(pop)
     tr = tn.transform(dp)
-    return {k: host(getattr(tr, k)) for k in (
-        "status", "n_valid", "order", "level", "row_ptr", "edge_src", "edge_row", "edge_w",
-        "pos_bias", "pos_resp", "pos_fn", "io_pos", "pos_row", "n_rows", "prog_node",
-        "prog_edge", "prog_rows", "prog_rec")}
+    return {k: host(getattr(tr, k)) for k in FIELDS}
 
 
 def blocks(pop, g):
@@ -254,6 +256,42 @@ def test_malformed_status_bits():
     st = got["status"][:pop.P]
     assert sorted(set(st.tolist())) == sorted(set(oracle.transform_arrays(pop)["status"]))
     assert (st != 0).sum() >= 12
+
+
+def test_size_classes_ordered_on_callers_stream():
+    """A ragged population of at least 2048 genomes is transformed by size
+    class on side streams forked from and joined back to the caller's stream.
+    On a non-default stream, copies of every output queued right after the
+    call, and a second call into the same arrays queued after the copies, see
+    the finished results: bitwise equal to a synchronised run's (both start
+    from the same sentinel, so unwritten padding compares equal too)."""
+    import torch
+    import paper_2504_08339_amd as tn
+    pop = synth.batching_population(P=2200)
+    assert int(np.diff(pop.node_off).max()) > 320   # the population spans every class
+    dp = to_device(pop)
+
+    def fresh():
+        tr = tn.Transformed(dp)
+        for k in FIELDS:
+            getattr(tr, k).view(torch.int32).fill_(-7)
+        return tr
+
+    ref = fresh()
+    tn.transform(dp, ref)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tr = fresh()
+        tn.transform(dp, tr)
+        copies = {k: getattr(tr, k).clone() for k in FIELDS}
+        tn.transform(dp, tr)
+        again = {k: getattr(tr, k).clone() for k in FIELDS}
+    s.synchronize()
+    for k in FIELDS:
+        assert torch.equal(copies[k].view(torch.int32), getattr(ref, k).view(torch.int32)), k
+        assert torch.equal(again[k].view(torch.int32), getattr(ref, k).view(torch.int32)), k
 
 
 def test_deterministic_reruns():
