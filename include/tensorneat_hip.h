@@ -241,7 +241,8 @@ int tn_pack_paper_layout(const float* PN, const float* PC, int32_t P, int32_t N_
  *   prog_edge conn block x 2 int32: {prog row of the source, bits of the weight},
  *                        followed by 8 padding entries after the whole array
  *                        (2 * (conn_elems + 8) int32 in all: the register
- *                        engine reads edges in groups of 8 ahead)
+ *                        engine reads edges in groups of 8 ahead and uses none
+ *                        past a node's last; the library never writes them)
  *   prog_rows [P]        rows the packed program uses (the largest number of
  *                        values live at once; 0 for a flagged genome)
  *   prog_rec node block x 16 int32: the packed program again, one record per
@@ -296,8 +297,9 @@ int tn_transformed_size(const tn_population* pop, tn_transformed_elems* out);
  * per device (default priority, non-blocking); they start after the work
  * already queued on `stream` and `stream` waits for them before anything
  * queued after this call, so the call is ordered on `stream` like a single
- * launch (also under stream capture). Calls from several host threads are
- * serialized while they queue their launches.
+ * launch. Calls from several host threads are serialized while they queue
+ * their launches. Under stream capture the classes are launched one after
+ * another on `stream` (no side streams join the capture).
  * Fills every array of *tr; the results do not depend on the launch shape. */
 int tn_transform(const tn_population* pop, const tn_transformed* tr, hipStream_t stream);
 

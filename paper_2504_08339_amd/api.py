@@ -182,6 +182,7 @@ class Transformed:
         self.n_rows = torch.empty(max(sz.genome_elems, 1), **i32)
         self.prog_node = torch.empty(4 * max(sz.node_elems, 1), **i32)
         self.prog_edge = torch.empty(2 * (max(sz.conn_elems, 1) + 8), **i32)  # + 8 padding
+        self.prog_edge[-16:].zero_()  # the library never writes the padding: keep it defined
         self.prog_rows = torch.empty(max(sz.genome_elems, 1), **i32)
         self.prog_rec = torch.empty(16 * max(sz.node_elems, 1), **i32)
         self.c = TnTransformed(*[_p(getattr(self, n), ty) for n, ty in (

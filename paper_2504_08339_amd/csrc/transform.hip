@@ -949,12 +949,21 @@ int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_
   }
   if (p.P == 0) return class_lds(cls[0]);  // nothing to launch; the LDS check still applies
   const int nc = (int)cls.size();
-  if (nc == 1) return launch_class(p, t, cls[0], stream);
   if (nc > kTfMaxClasses) return TN_EUNSUPPORTED;
+  // Under stream capture the classes go one after another on the caller's
+  // stream: side streams that joined a capture stay in it until it ends, and
+  // they are shared with every other call on the device.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  int rc = record_hip(hipStreamIsCapturing(stream, &cap));
+  if (rc != TN_OK) return rc;
+  if (nc == 1 || cap != hipStreamCaptureStatusNone) {
+    for (int i = nc - 1; i >= 0 && rc == TN_OK; --i) rc = launch_class(p, t, cls[i], stream);
+    return rc;
+  }
 
   std::lock_guard<std::mutex> lock(g_class_mu);
   ClassStreams* cs = nullptr;
-  int rc = class_streams(&cs);
+  rc = class_streams(&cs);
   if (rc == TN_OK) rc = record_hip(hipEventRecord(cs->fork, stream));
   if (rc != TN_OK) return rc;
   // largest class first, on the caller's stream

@@ -294,6 +294,41 @@ def test_size_classes_ordered_on_callers_stream():
         assert torch.equal(again[k].view(torch.int32), getattr(ref, k).view(torch.int32)), k
 
 
+def test_size_classes_under_graph_capture():
+    """Captured into a graph, the size classes of a large ragged population are
+    launched one after another on the capturing stream. Three replays, each
+    after an eager sentinel fill and a synchronisation, each equal the eager
+    call bit for bit."""
+    import torch
+    import paper_2504_08339_amd as tn
+    pop = synth.batching_population(P=2100)
+    dp = to_device(pop)
+    ref = tn.Transformed(dp)
+    for k in FIELDS:
+        getattr(ref, k).view(torch.int32).fill_(-7)
+    tn.transform(dp, ref)
+    torch.cuda.synchronize()
+    tr = tn.Transformed(dp)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tn.transform(dp, tr)          # eager warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        tn.transform(dp, tr)
+    for rep in range(3):
+        for k in FIELDS:
+            getattr(tr, k).view(torch.int32).fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in FIELDS:
+            assert torch.equal(getattr(tr, k).view(torch.int32),
+                               getattr(ref, k).view(torch.int32)), (rep, k)
+
+
 def test_deterministic_reruns():
     pop = synth.batching_population(P=300)
     a = run_transform(pop)
