@@ -858,7 +858,7 @@ namespace {
 // genomes). Side streams (default priority, non-blocking) and events are made
 // once per device; the mutex keeps the fork / launch / join sequence of one
 // call from interleaving with another's on the same events.
-constexpr int kTfMaxClasses = 4;
+constexpr int kTfMaxClasses = 5;
 constexpr int kMaxDevices = 64;
 struct ClassStreams {
   hipStream_t side[kTfMaxClasses - 1] = {};
@@ -929,7 +929,7 @@ int launch_transform(const tn_population& p, const tn_transformed& t, hipStream_
   std::vector<Layout> cls;
   if (p.node_off && p.P >= kTfClassMinGenomes) {
     int n_prev = -1, c_prev = -1;
-    for (int n : {96, 192, 320}) {
+    for (int n : {96, 192, 320, 400}) {
       const int c = std::min(p.C_max, 4 * n);
       if (n >= p.N_max) break;
       Layout L = make_layout(n, c);

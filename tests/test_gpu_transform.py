@@ -141,8 +141,8 @@ def test_large_ragged_population_by_size_class():
     assert (got["status"][:pop.P][over] == oracle.OVERSIZE).all()
     assert (got["status"][:pop.P][~over] == 0).all()
     crows = np.diff(c_off)
-    near = [g for g in range(pop.P) if any(abs(int(rows[g]) - b) <= 2 for b in (96, 192, 320))
-            or any(abs(int(crows[g]) - b) <= 8 for b in (384, 768, 1280))]
+    near = [g for g in range(pop.P) if any(abs(int(rows[g]) - b) <= 2 for b in (96, 192, 320, 400))
+            or any(abs(int(crows[g]) - b) <= 8 for b in (384, 768, 1280, 1600))]
     sample = sorted(set(padded_ids.tolist()) | set(near[:120]) |
                     set(rng.choice(pop.P, size=120, replace=False).tolist()) |
                     set(np.flatnonzero(over).tolist()))
@@ -268,7 +268,7 @@ def test_size_classes_ordered_on_callers_stream():
     import torch
     import paper_2504_08339_amd as tn
     pop = synth.batching_population(P=2200)
-    assert int(np.diff(pop.node_off).max()) > 320   # the population spans every class
+    assert int(np.diff(pop.node_off).max()) > 400   # the population spans every class
     dp = to_device(pop)
 
     def fresh():
