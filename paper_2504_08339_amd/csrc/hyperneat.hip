@@ -158,12 +158,15 @@ cppn_query_kernel(PopView pop, const int32_t* __restrict__ status,
 // ----------------------------------------------------------------- hidden
 
 // Batched C[g][m][n] = sum_k A[g][m][k] * B[g][n][k] (bfloat16 operands, both
-// contiguous along k; float32 accumulation), one wavefront per 64 x 64 tile of
-// C: K steps of 32 with 16 MFMA 16x16x32 per step. Operand fragments are
-// loaded straight from global memory (16 bytes per lane: 8 consecutive k of
-// one row), with the same k-ordering on both operands. Rows m >= M or n >= N
-// read zeros and are not stored; K is a multiple of 32. kTanh applies tanh in
-// the epilogue (the substrate's hidden layer).
+// contiguous along k; float32 accumulation). A workgroup of four wavefronts
+// computes a 128 x 128 tile of C, each wavefront a 64 x 64 quarter with MFMA
+// 16x16x32. K runs in stages of 64: while the wavefronts multiply from one LDS
+// buffer, every thread fetches its 16-byte chunks of the next stage's A and B
+// rows into registers and then writes them to the other buffer, one barrier
+// per stage. Rows m >= M, n >= N and columns k >= K read zeros and are not
+// stored; K is a multiple of 32. kTanh applies tanh in the epilogue (the
+// substrate's hidden layer). The tiles of one batch entry are consecutive
+// workgroups kept on one XCD, so its operands come from HBM once.
 struct GemmArgs {
   const uint16_t* a;
   int64_t lda, a_batch;
@@ -176,76 +179,152 @@ struct GemmArgs {
   int64_t n_items;
 };
 
+constexpr int kGemmTile = 128;              // rows of C per workgroup, both ways
+constexpr int kGemmKs = 64;                 // k per stage
+constexpr int kGemmRow = kGemmKs + 8;       // bf16 per LDS row (16 bytes of padding)
+constexpr int kGemmBuf = kGemmTile * kGemmRow;  // bf16 per operand buffer
+constexpr size_t kGemmLds = sizeof(uint16_t) * 4 * kGemmBuf;  // A and B, two buffers each
+
+// Workgroup b of n runs on XCD b mod 8; returns the item it takes so that
+// consecutive items share an XCD (the last n mod 8 in order).
+__device__ __forceinline__ int64_t gemm_item(int64_t b, int64_t n) {
+  constexpr int kXcd = 8;
+  const int64_t per = n / kXcd, full = per * kXcd;
+  if (b >= full) return b;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// 16 bytes from global memory (the operands arrive as pointers in a struct
+// argument, whose address space the compiler cannot infer)
+__device__ __forceinline__ u32x4 load_global16(const uint16_t* q) {
+  return *(const __attribute__((address_space(1))) u32x4*)q;
+}
+__device__ __forceinline__ void store_global(float* q, float v) {
+  *(__attribute__((address_space(1))) float*)q = v;
+}
+
 template <bool kTanh>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs p) {
-  const int lane = lane_id();
-  const int wave = wave_id();
-  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-  if (item >= p.n_items) return;  // wavefront-uniform; the kernel has no barrier
+  extern __shared__ __align__(16) uint16_t gemm_lds[];
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int64_t item = gemm_item(blockIdx.x, gridDim.x);
   const int per_g = p.m_tiles * p.n_tiles;
   const int g = (int)(item / per_g);
   const int r = (int)(item - (int64_t)g * per_g);
-  // the m tiles of one n tile are consecutive items (one workgroup): their
-  // B rows are read once, from one L2
   const int nt = r / p.m_tiles, mt = r - nt * p.m_tiles;
-  const int m0 = mt * 64, n0 = nt * 64;
+  const int m0 = mt * kGemmTile, n0 = nt * kGemmTile;
   const uint16_t* A = p.a + (int64_t)g * p.a_batch;
   const uint16_t* Bm = p.b + (int64_t)g * p.b_batch;
+  uint16_t* sa = gemm_lds;                 // [2][kGemmBuf]
+  uint16_t* sb = gemm_lds + 2 * kGemmBuf;  // [2][kGemmBuf]
+
+  // this thread's chunks of a stage: chunk c = tid + 256 u is row c / 8,
+  // k (c % 8) * 8 .. + 7 of the stage
+  constexpr int kChunks = kGemmTile * kGemmKs / 8 / 256;
+  struct Regs {
+    u32x4 a[kChunks], b[kChunks];
+  };
+  const u32x4 zero4 = {0u, 0u, 0u, 0u};
+  auto fetch = [&](int st, Regs& r) {
+    const int k0 = st * kGemmKs;
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const int c = tid + 256 * u, row = c >> 3, k = k0 + (c & 7) * 8;
+      const bool kin = k < p.K;
+      r.a[u] = m0 + row < p.M && kin ? load_global16(A + (int64_t)(m0 + row) * p.lda + k) : zero4;
+      r.b[u] = n0 + row < p.N && kin ? load_global16(Bm + (int64_t)(n0 + row) * p.ldb + k) : zero4;
+    }
+  };
+  auto stash = [&](int buf, const Regs& r) {
+#pragma unroll
+    for (int u = 0; u < kChunks; ++u) {
+      const int c = tid + 256 * u, at = (c >> 3) * kGemmRow + (c & 7) * 8;
+      *reinterpret_cast<u32x4*>(sa + buf * kGemmBuf + at) = r.a[u];
+      *reinterpret_cast<u32x4*>(sb + buf * kGemmBuf + at) = r.b[u];
+    }
+  };
+
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;  // this wavefront's quarter
   const int li = lane & 15, kq = (lane >> 4) * 8;
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
-  const bf16x8 zero8 = {};
-  // the fragments of step k0 + 32 are loaded while step k0's MFMAs run
-  bf16x8 a[4], b[4], an[4], bn[4];
-  auto load = [&](int k0, bf16x8(&fa)[4], bf16x8(&fb)[4]) {
+  auto multiply = [&](int buf) {
+    const uint16_t* pa = sa + buf * kGemmBuf + (wm + li) * kGemmRow + kq;
+    const uint16_t* pb = sb + buf * kGemmBuf + (wn + li) * kGemmRow + kq;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra = m0 + 16 * i + li, rb = n0 + 16 * i + li;
-      fa[i] = ra < p.M ? *reinterpret_cast<const bf16x8*>(A + ra * p.lda + k0 + kq) : zero8;
-      fb[i] = rb < p.N ? *reinterpret_cast<const bf16x8*>(Bm + rb * p.ldb + k0 + kq) : zero8;
+    for (int kk = 0; kk < kGemmKs; kk += 32) {
+      bf16x8 fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fa[i] = *reinterpret_cast<const bf16x8*>(pa + 16 * i * kGemmRow + kk);
+        fb[i] = *reinterpret_cast<const bf16x8*>(pb + 16 * i * kGemmRow + kk);
+      }
+      // B as the first operand: the fragment is the 16 x 16 block of C
+      // transposed, so a lane ends up with four consecutive columns of a row
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j], fa[i], acc[i][j], 0, 0, 0);
     }
   };
-  load(0, a, b);
-  for (int k0 = 0; k0 < p.K; k0 += 32) {
-    if (k0 + 32 < p.K) load(k0 + 32, an, bn);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a[i] = an[i];
-      b[i] = bn[i];
-    }
+  // Stage st sits in LDS buffer st % 2 while the wavefronts multiply it; the
+  // next stage is requested to registers before the multiply and written to
+  // the other buffer after it, which was last read before the previous
+  // barrier. (Two stages in flight need a second register set: 352 registers,
+  // one wavefront per SIMD, or spills when held to two.)
+  const int n_stages = (p.K + kGemmKs - 1) / kGemmKs;
+  Regs rg;
+  fetch(0, rg);
+  stash(0, rg);
+  __syncthreads();
+  for (int st = 0; st < n_stages; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < n_stages;
+    if (more) fetch(st + 1, rg);
+    multiply(buf);
+    if (more) stash(buf ^ 1, rg);
+    __syncthreads();
   }
   float* C = p.c + (int64_t)g * p.c_batch;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      // the fragment of D = C^T holds rows 4 (lane / 16) + e, column lane % 16:
+      // C row lane % 16, columns 4 (lane / 16) + e of the block
+      const int row = m0 + wm + 16 * i + li;
+      const int col = n0 + wn + 16 * j + (lane >> 4) * 4;
+      if (row >= p.M) continue;
+      float v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // D[16x16] fragment: lane holds rows 4*(lane/16) + e, column lane % 16
-        const int row = m0 + 16 * i + (lane >> 4) * 4 + e;
-        const int col = n0 + 16 * j + li;
-        if (row < p.M && col < p.N)
-          C[row * p.ldc + col] = kTanh ? act_tanh(acc[i][j][e]) : acc[i][j][e];
+      for (int e = 0; e < 4; ++e) v[e] = kTanh ? act_tanh(acc[i][j][e]) : acc[i][j][e];
+      float* q = C + (int64_t)row * p.ldc + col;
+      if (col + 3 < p.N && (p.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0) {
+        f32x4 w = {v[0], v[1], v[2], v[3]};
+        *(__attribute__((address_space(1))) f32x4*)q = w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < p.N) store_global(q + e, v[e]);
       }
+    }
 }
 
 template <bool kTanh>
 int launch_gemm(GemmArgs p, int batch, hipStream_t stream) {
-  p.m_tiles = (p.M + 63) / 64;
-  p.n_tiles = (p.N + 63) / 64;
+  p.m_tiles = (p.M + kGemmTile - 1) / kGemmTile;
+  p.n_tiles = (p.N + kGemmTile - 1) / kGemmTile;
   p.n_items = (int64_t)batch * p.m_tiles * p.n_tiles;
-  if (p.n_items == 0) return TN_OK;
-  const int64_t grid = (p.n_items + 3) / 4;
-  if (grid > 0x7fffffff) return TN_EUNSUPPORTED;
-  hipLaunchKernelGGL((gemm_nt_kernel<kTanh>), dim3((unsigned)grid), dim3(256), 0, stream, p);
+  const int rc = allow_lds((const void*)gemm_nt_kernel<kTanh>, kGemmLds);
+  if (rc != TN_OK || p.n_items == 0) return rc;
+  if (p.n_items > 0x7fffffff) return TN_EUNSUPPORTED;
+  hipLaunchKernelGGL((gemm_nt_kernel<kTanh>), dim3((unsigned)p.n_items), dim3(256), kGemmLds,
+                     stream, p);
   return check_launch();
 }
 
