@@ -152,8 +152,10 @@ __device__ __forceinline__ void rf_node(const Rec& w, const int2* __restrict__ p
   float s[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) s[k] = 0.0f;
-  if (agg == TN_AGG_SUM) {
-    if (ne > 0) {
+  if (ne <= 0) {
+    // no in-edges: the aggregate is 0 whatever the aggregation
+  } else if (agg == TN_AGG_SUM) {
+    {
       rfk_fma<R>(s, __int_as_float(w(5)), w(4));
       if (ne > 1) {
         rfk_fma<R>(s, __int_as_float(w(7)), w(6));
@@ -182,7 +184,7 @@ __device__ __forceinline__ void rf_node(const Rec& w, const int2* __restrict__ p
         }
       }
     }
-  } else if (ne > 0) {
+  } else {
     // other aggregations: terms in order
     const int r0 = w(4), w0 = w(5);
 #pragma unroll
