@@ -164,14 +164,14 @@ struct LdsProgT {
   const EdgeRec* edges;
   __device__ __forceinline__ NodeRec node(int p) const {
     const int4 q = reinterpret_cast<const int4*>(recs)[p];
+    // all four words used here: the read is not split around the
+    // input-position test that follows (inputs only, so nothing is copied)
+    asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
     NodeRec r;
     r.erange = q.x;
     r.fn = q.y;
     r.bias = __int_as_float(q.z);
     r.resp = __int_as_float(q.w);
-    // all four words in registers here: the read is not split around the
-    // input-position test that follows
-    asm volatile("" : "+v"(r.erange), "+v"(r.fn), "+v"(r.bias), "+v"(r.resp));
     return r;
   }
   __device__ __forceinline__ EdgeRec edge(int e) const { return edges[e]; }
