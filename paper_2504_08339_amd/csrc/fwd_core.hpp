@@ -248,15 +248,23 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
   if (agg == TN_AGG_SUM) {
 #pragma unroll
     for (int k = 0; k < K; ++k) s[k] = 0.0f;
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) sum_edges<4, K, kRow>(prog, e, mine, s);
     // the last one to three in-edges unrolled: their records requested
-    // together, then their source values
-    switch (e1 - e) {
-      case 1: sum_edges<1, K, kRow>(prog, e, mine, s); break;
-      case 2: sum_edges<2, K, kRow>(prog, e, mine, s); break;
-      case 3: sum_edges<3, K, kRow>(prog, e, mine, s); break;
-      default: break;
+    // together, then their source values; most nodes have no more than
+    // three, so that case comes first (same order of terms either way)
+    auto tail = [&](int e) {
+      switch (e1 - e) {
+        case 1: sum_edges<1, K, kRow>(prog, e, mine, s); break;
+        case 2: sum_edges<2, K, kRow>(prog, e, mine, s); break;
+        case 3: sum_edges<3, K, kRow>(prog, e, mine, s); break;
+        default: break;
+      }
+    };
+    if (__builtin_expect(e1 - e0 < 4, 1)) {
+      tail(e0);
+    } else {
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) sum_edges<4, K, kRow>(prog, e, mine, s);
+      tail(e);
     }
   } else if (e0 == e1) {
 #pragma unroll
