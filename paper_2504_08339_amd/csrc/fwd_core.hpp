@@ -302,7 +302,7 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
   float z[K], v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) z[k] = fmaf(rec.resp, s[k], rec.bias);
-  activate_all<K>(f & 0xff, z, v);
+  activate_all<K>(f & 7, z, v);  // codes below 7, checked by the transformation
   Vec<K> out;
 #pragma unroll
   for (int k = 0; k < K; ++k) out.x[k] = v[k];
