@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kWave) void backward_kernel(
       const NodeRec rec = recs[p];
       const int f = __builtin_amdgcn_readfirstlane(rec.fn);
       if (f < 0) continue;
-      const int act = f & 0xff, agg = (f >> 8) & 0xff;
+      const int act = f & 7, agg = (f >> 8) & 0xff;  // codes below 7: transformed genomes
       const float vp = v[p * kRow + lane];
       const float z = slope_needs_z(act) ? node_z(rec, f, edges, v, lane) : 0.0f;
       const float delta = live ? gr[p * kRow + lane] * act_slope(act, vp, z) : 0.0f;
@@ -439,9 +439,9 @@ backward_rf_kernel(PopView pop, const int32_t* __restrict__ status,
       // interleaving them: less register pressure in sin's reduction)
       const float z0[1] = {fmaf(rho, sum[0], bias)}, z1[1] = {fmaf(rho, sum[1], bias)};
       float v0[1], v1[1];
-      activate_all<1>(f & 0xff, z0, v0);
+      activate_all<1>(f & 7, z0, v0);  // codes below 7: transformed genomes
       asm volatile("" : "+v"(v0[0]));
-      activate_all<1>(f & 0xff, z1, v1);
+      activate_all<1>(f & 7, z1, v1);
       bw_set_v(p, v0[0], v1[0]);
     }
     // upstream gradient at the outputs
@@ -470,7 +470,7 @@ backward_rf_kernel(PopView pop, const int32_t* __restrict__ status,
     for (int p = n - 1; p >= 0; --p) {
       const int f = __builtin_amdgcn_readlane(l_fn, p);
       if (f < 0) continue;
-      const int act = f & 0xff;
+      const int act = f & 7;
       const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);
       const bool mean = ((f >> 8) & 0xff) == TN_AGG_MEAN && e1 > e0;
       const float rho = __int_as_float(__builtin_amdgcn_readlane(l_resp, p));

@@ -675,7 +675,7 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
       const float bias = __int_as_float(__builtin_amdgcn_readlane(l_bias, p));
       const float z[2] = {fmaf(rho, s0, bias), fmaf(rho, s1, bias)};
       float v[2];
-      activate_all<2>(f & 0xff, z, v);
+      activate_all<2>(f & 7, z, v);  // codes below 7 (flagged genomes return above)
       adj_set_vz(p, v[0], v[1], z[0], z[1]);
     }
     float y0, y1;
@@ -689,7 +689,7 @@ cppn_backward_kernel(PopView pop, const int32_t* __restrict__ status,
       if (f < 0) continue;
       float g0, g1, v0, v1, z0, z1;
       adj_get_gvz(p, g0, g1, v0, v1, z0, z1);
-      const int act = f & 0xff;
+      const int act = f & 7;
       const float d0 = g0 * cppn_slope(act, v0, z0), d1 = g1 * cppn_slope(act, v1, z1);
       acc[(KE + p) * kWave] += d0 + d1;
       const int e0 = __builtin_amdgcn_readlane(l_rp, p), e1 = __builtin_amdgcn_readlane(l_rp, p + 1);

@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void recurrent_kernel(PopView pop, const fl
           if (agg == TN_AGG_MEAN) s = s / (float)(e1 - e0);
         }
         float z[1] = {fmaf(__int_as_float(q.w), s, __int_as_float(q.z))}, v[1];
-        activate_all<1>(f & 0xff, z, v);
+        activate_all<1>(f & 7, z, v);  // codes below 7: checked above
         nxt[r * kWave + lane] = v[0];
       }
       __syncthreads();
