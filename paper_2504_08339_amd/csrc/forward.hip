@@ -141,10 +141,14 @@ __device__ __forceinline__ void lds_genome(
     for (int k = threadIdx.x; k < nio; k += T)
       io_l[k] = pos_row[nb + io_pos[(int64_t)g * nio + k]];
     if (kProgLds) {
+      constexpr int kRowBytes = (int)(sizeof(float) * (kWave + 1) * K);
       for (int p = threadIdx.x; p < n; p += T) {
         NodeRec r;
         r.erange = row_ptr[rb + p] | (row_ptr[rb + p + 1] << 16);
-        r.fn = fn_with_row(fn[nb + p], pos_row[nb + p]);
+        // act | agg << 3 | byte offset of the value row << 6 (LdsProgT<true>)
+        const int f0 = fn[nb + p];
+        r.fn = f0 < 0 ? f0
+                      : (f0 & 0xff) | (((f0 >> 8) & 0xff) << 3) | ((pos_row[nb + p] * kRowBytes) << 6);
         r.bias = __int_as_float(bias_bits[nb + p]);
         r.resp = __int_as_float(resp_bits[nb + p]);
         recs[p] = r;
@@ -152,7 +156,6 @@ __device__ __forceinline__ void lds_genome(
       // two in-edges per thread and step, both sources' row loads in flight
       // together
       const int n_edges = row_ptr[rb + n];
-      constexpr int kRowBytes = (int)(sizeof(float) * (kWave + 1) * K);
       for (int e = threadIdx.x; e < n_edges; e += 2 * T) {
         const int e2 = e + T;
         const bool two = e2 < n_edges;

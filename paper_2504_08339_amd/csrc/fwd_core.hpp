@@ -157,9 +157,13 @@ __host__ __device__ __forceinline__ int32_t fn_with_row(int32_t fn, int32_t row)
 // 16-byte load. kSrcBytes: the in-edge records hold the byte offset of the
 // source row (row * kRow * 4) instead of its index, which saves a 32-bit
 // multiply per in-edge.
+// kBytes also changes the node's function word: act | agg << 3 | (byte offset
+// of its value row) << 6 (negative for an input position), so the row's
+// address needs no multiply.
 template <bool kBytes>
 struct LdsProgT {
   static constexpr bool kSrcBytes = kBytes;
+  static constexpr bool kDstBytes = kBytes;
   const NodeRec* recs;
   const EdgeRec* edges;
   __device__ __forceinline__ NodeRec node(int p) const {
@@ -183,6 +187,7 @@ using LdsProg = LdsProgT<false>;
 // cannot alias them and the loads stay scalar.
 struct GlobalProg {
   static constexpr bool kSrcBytes = false;
+  static constexpr bool kDstBytes = false;
   const int32_t* rp;
   const int32_t* fn;
   const int32_t* bias;
@@ -243,7 +248,7 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
   if (f < 0) return;
   const int er = __builtin_amdgcn_readfirstlane(rec.erange);
   const int e0 = er & 0xffff, e1 = (er >> 16) & 0xffff;
-  const int agg = (f >> 8) & 0xff;
+  const int agg = Prog::kDstBytes ? (f >> 3) & 7 : (f >> 8) & 0xff;
   float s[K];
   if (agg == TN_AGG_SUM) {
 #pragma unroll
@@ -306,7 +311,10 @@ __device__ __forceinline__ void eval_node(const Prog& prog, int p, float* mine) 
   Vec<K> out;
 #pragma unroll
   for (int k = 0; k < K; ++k) out.x[k] = v[k];
-  out.store(mine + ((f >> 16) & 0x7fff) * kRow);
+  if constexpr (Prog::kDstBytes)
+    out.store(reinterpret_cast<float*>(reinterpret_cast<char*>(mine) + (f >> 6)));
+  else
+    out.store(mine + ((f >> 16) & 0x7fff) * kRow);
 }
 
 }  // namespace tn
