@@ -42,8 +42,11 @@ struct RegArgs {
 // Persistent form, XCD-aware: workgroup b runs on XCD b % 8 (the round-robin
 // dispatch of MI355X's 8 XCDs); the list entries e with e % 8 == x form XCD
 // x's share, taken from counter x, so that the units of one genome run under
-// one L2 and its program is fetched from HBM once. Entry and unit of item i of
-// share x (items: entry-major, units consecutive).
+// one L2 and its program is fetched from HBM once. The placement matters for
+// speed only: share x is drained by the workgroups with b % 8 == x wherever
+// they run, and the launcher rounds the grid up to a multiple of 8 so every
+// share has some. Entry and unit of item i of share x (items: entry-major,
+// units consecutive).
 constexpr int kXcds = 8;
 __device__ __forceinline__ int share_items(int n_list, int x, int units) {
   return n_list > x ? ((n_list - x + kXcds - 1) / kXcds) * units : 0;
