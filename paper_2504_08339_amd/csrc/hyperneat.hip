@@ -9,8 +9,9 @@
 //            packed program runs in registers (the register engine's walk);
 //            weights are stored transposed, w1t[t][s] and w2t[j][s], so that
 //            both GEMM operands are contiguous along the reduction index.
-//   hidden   H = tanh(X W1): v_mfma_f32_16x16x32_bf16, one wavefront per
-//            64 x 64 tile of H, fp32 accumulation, tanh in the epilogue.
+//   hidden   H = tanh(X W1): v_mfma_f32_16x16x32_bf16, a workgroup of four
+//            wavefronts per 128 x 128 tile of H with K staged through LDS,
+//            fp32 accumulation, tanh in the epilogue.
 //   output   Y = bf16(H) W2 with fp32 accumulation in a fixed order.
 // Geometry: an n x n grid layer has node n*r + c at (-1 + 2c/(n-1),
 // -1 + 2r/(n-1)); output j of m sits at (-1 + 2j/(m-1), 0).
